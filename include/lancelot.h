@@ -1,0 +1,210 @@
+/*
+ * lancelot.h -- C ABI of the MI355X (gfx950) engine for Lancelot's encrypted
+ * pairwise squared distances (arXiv 2408.06197): RNS-CKKS over
+ * Z_Q[X]/(X^N + 1) with hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Moduli.  A context holds the chain q_0..q_L (n_q = L+1 limbs) and the
+ *   special primes p_0..p_{K-1} (n_p = K) of hybrid key switching.  Digit
+ *   size alpha = K, dnum = ceil((L+1)/alpha).  Every modulus has at most 50
+ *   bits.  Prime rule: for each requested bit size b, in order, the largest
+ *   b-bit prime k*2^log_m + 1 not already chosen.
+ * Layouts.  Device buffers of uint64 residues in [0, q_l), limb-major:
+ *   plaintext [n_q][N], ciphertext [2][n_q][N], triple [3][n_q][N].  A batch
+ *   of `count` objects is contiguous: [count][comp][n_q][N].  Ciphertexts and
+ *   triples are in the NTT domain: entry i of a limb is the value at
+ *   psi^(2 brev(i) + 1), psi the smallest primitive 2N-th root mod q_l.
+ * Ownership.  The caller allocates and frees every buffer it passes; a
+ *   pointer argument named *_dev is device memory on the context's device,
+ *   *_host is host memory.  The library owns its parameter tables, resident
+ *   keys and a workspace it grows on demand (hipMalloc) and frees at
+ *   lc_ctx_destroy.
+ * Streams.  `stream` is a hipStream_t (NULL: the default stream).  Device
+ *   calls are asynchronous on it; lc_sync waits and reports asynchronous
+ *   errors.  Calls on one context must come from one host thread at a time.
+ * Errors.  Every call returns LC_OK (0) or a negative code; lc_last_error
+ *   gives text.  Nothing is written to outputs when a call returns an error
+ *   before launching work.
+ * Roles.  A LC_ROLE_KGC context may hold the secret key; a LC_ROLE_SERVER
+ *   context holds only public and evaluation keys (the server of the threat
+ *   model is semi-honest, Methods, Threat Model).  Decryption and key
+ *   generation need LC_ROLE_KGC (else LC_EKEY).
+ */
+#ifndef LANCELOT_H
+#define LANCELOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LC_OK 0
+#define LC_EINVAL (-1)  /* bad argument: shape, size, level, plan        */
+#define LC_ENOMEM (-2)  /* device allocation failed                       */
+#define LC_EKEY (-3)    /* missing key, or secret-key use in server role  */
+#define LC_EHIP (-4)    /* HIP runtime error                              */
+#define LC_EUNSUP (-5)  /* parameters outside what the kernels support    */
+
+#define LC_ROLE_SERVER 0
+#define LC_ROLE_KGC 1
+
+typedef struct lc_ctx lc_ctx;
+
+/* Parameter set (Methods, CKKS Scheme Description: N, Q = prod q_i, special
+ * modulus p; hybrid decomposition of Dynamic Hoisting).  log_n in [3, 16];
+ * 1 <= n_q <= 48, 1 <= n_p <= 8; bit sizes in [20, 50]; log_m = 0 means
+ * log_n + 1, otherwise log_m >= log_n + 1. */
+typedef struct lc_params {
+    int log_n;
+    int n_q;
+    int n_p;
+    const int *q_bits;
+    const int *p_bits;
+    int log_m;
+} lc_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Builds primes, NTT twiddles and base-conversion tables on `device`.
+ * device = -1 makes a host-only context: primes, encode/decode, CRT and the
+ * Gaussian table work; every device call returns LC_EUNSUP. */
+int lc_ctx_create(const lc_params *prm, int device, int role, lc_ctx **out);
+int lc_ctx_destroy(lc_ctx *ctx);
+const char *lc_last_error(const lc_ctx *ctx);
+/* Copies the n_q + n_p moduli (q's then p's) to host memory. */
+int lc_ctx_moduli(const lc_ctx *ctx, uint64_t *moduli_host);
+/* Any pointer may be NULL. */
+int lc_ctx_info(const lc_ctx *ctx, int *log_n, int *n_q, int *n_p, int *dnum);
+int lc_sync(lc_ctx *ctx, void *stream);
+/* Bytes of library-owned device memory (tables, keys, workspace). */
+int lc_ctx_device_bytes(const lc_ctx *ctx, size_t *bytes);
+
+/* ---- keys (KGC role) ----------------------------------------------------- */
+
+/* Secret s (ternary), public key pk = ([-a s + e]_Q, a) and the
+ * relinearization key for s^2 (CKKS Scheme Description, key generation, in
+ * the hybrid dnum-digit form).  Draws come from Philox4x64-10 keyed
+ * (seed, 0): word w of (domain, object) is lane w % 4 of the block at counter
+ * (w / 4, object, domain, 0).  Domains: 1 secret, 2 pk.a (object = limb),
+ * 3 pk.e, 4/5/6 encryption r/e0/e1 (object = plaintext id), 7 key a (object =
+ * key_id << 32 | digit << 16 | limb), 8 key e (object = key_id << 32 | digit);
+ * key_id is 0 for the relinearization key and the Galois element of a
+ * rotation key.  Ternary = word mod 3 - 1; Gaussian = smallest t in
+ * [-19, 19] with word < T[t] (sigma 3.2 cumulative table); uniform mod q =
+ * (word[2c] * 2^64 + word[2c+1]) mod q.  Synchronous. */
+int lc_keygen(lc_ctx *ctx, uint64_t seed);
+/* Rotation keys for slot rotations by steps[t] (Galois element 5^step). */
+int lc_keygen_rotation(lc_ctx *ctx, uint64_t seed, const int *steps, int nsteps);
+/* Copies pk, relin and rotation keys (never the secret) into `dst`, which
+ * must have identical parameters and device. */
+int lc_keys_share(const lc_ctx *src, lc_ctx *dst);
+/* Secret coefficients in {-1, 0, 1} to host int64[N] (KGC role only). */
+int lc_secret_export(const lc_ctx *ctx, int64_t *s_host);
+/* Public key [2][n_q][N] to host. */
+int lc_pk_export(const lc_ctx *ctx, uint64_t *pk_host);
+/* Key-switching key [dnum][2][n_q+n_p][N] to host: which = 0 relin key,
+ * which = 1 rotation key for `step`. */
+int lc_ksk_export(const lc_ctx *ctx, int which, int step, uint64_t *ksk_host);
+
+/* ---- encode / decode (host, FP64; Methods, Batch Encoding and Decoding) -- */
+
+/* m = round(scale * sigma^-1(pi^-1(z))), z real (z_im NULL) or complex with
+ * nslots <= N/2 slots (missing slots are zero).  m_host: int64[N]. */
+int lc_encode(const lc_ctx *ctx, const double *z_re, const double *z_im, size_t nslots, double scale,
+              int64_t *m_host);
+/* Decode a coefficient-domain plaintext given as residues [n_q][N] (host):
+ * exact CRT to centred integers, then z = pi(sigma(m)) / scale. */
+int lc_decode(const lc_ctx *ctx, const uint64_t *res_host, double scale, double *z_re, double *z_im);
+/* Exact CRT of `ncoeff` coefficients: res_host is [n_q][stride], coefficient
+ * t of limb l at res_host[l * stride + t]; out[t] = centred value as double. */
+int lc_crt_to_double(const lc_ctx *ctx, const uint64_t *res_host, size_t ncoeff, size_t stride, double *out);
+/* The 38 thresholds of the sigma = 3.2 error sampler (entry k belongs to
+ * t = k - 19) to host memory. */
+int lc_gaussian_table(const lc_ctx *ctx, uint64_t *out38);
+
+/* ---- encryption / decryption ---------------------------------------------- */
+
+/* ct = ([m + r u0 + e0]_Q, [r u1 + e1]_Q) (CKKS Scheme Description,
+ * encryption) for `count` plaintexts m_dev int64[count][N] (coefficients,
+ * |m| < 2^62).  r ternary, e Gaussian sigma 3.2; plaintext t draws from PRNG
+ * object first_object + t.  ct_dev [count][2][n_q][N]. */
+int lc_encrypt(lc_ctx *ctx, const int64_t *m_dev, size_t count, uint64_t seed, uint64_t first_object,
+               uint64_t *ct_dev, void *stream);
+/* [c0 + c1 s (+ c2 s^2)]_Q in the coefficient domain (CKKS Scheme
+ * Description, decryption; ncomp 3 reads a triple).  in [count][ncomp][n_q][N],
+ * out [count][n_q][N].  KGC role. */
+int lc_decrypt(lc_ctx *ctx, const uint64_t *ct_dev, int ncomp, size_t count, uint64_t *pt_dev, void *stream);
+
+/* ---- homomorphic operations (CKKS Scheme Description, evaluation; Methods,
+ * Private Distance Evaluation) --------------------------------------------- */
+
+/* out = a -/+ b limb-wise for count ciphertexts of ncomp components. */
+int lc_ct_sub(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out_dev, size_t count,
+              int ncomp, void *stream);
+int lc_ct_add(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out_dev, size_t count,
+              int ncomp, void *stream);
+/* Triple (a0 b0, a0 b1 + a1 b0, a1 b1) without relinearization. */
+int lc_ct_mul(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out3_dev, size_t count,
+              void *stream);
+/* Triple (a0^2, 2 a0 a1, a1^2). */
+int lc_ct_square(lc_ctx *ctx, const uint64_t *a_dev, uint64_t *out3_dev, size_t count, void *stream);
+/* Relinearization of triples with the s^2 key: out = (d0 + KS0(d2),
+ * d1 + KS1(d2)), hybrid key switching (Methods, Lazy Relinearization and
+ * Dynamic Hoisting).  in [count][3][n_q][N], out [count][2][n_q][N]; out must
+ * not overlap in (LC_EINVAL). */
+int lc_relin(lc_ctx *ctx, const uint64_t *ct3_dev, uint64_t *ct2_dev, size_t count, void *stream);
+/* Hoisted rotations (Methods, Dynamic Hoisting): one decomposition/ModUp of
+ * c1 shared by all steps, then per step the automorphism on the raised
+ * digits, the key inner product and ModDown.  outs [count][nsteps][2][n_q][N],
+ * not overlapping ct; 1 <= nsteps <= 64; a missing key gives LC_EKEY. */
+int lc_rotate_hoisted(lc_ctx *ctx, const uint64_t *ct_dev, size_t count, const int *steps, int nsteps,
+                      uint64_t *outs_dev, void *stream);
+/* Rotate-and-sum in place (Methods, Dynamic Hoisting): after it every slot
+ * holds the sum of all N/2 slots.  plan[b] = levels of block b (sum =
+ * log_n - 1); block b starting at level j0 adds rot_{t 2^j0} for t = 1 ..
+ * 2^plan[b] - 1 with one ModUp and one ModDown.  plan NULL = all ones. */
+int lc_rotate_sum(lc_ctx *ctx, uint64_t *ct_dev, size_t count, const int *plan, int nblocks, void *stream);
+/* out = ct * pt per component, pt [n_q][N] NTT domain, one pt per ct. */
+int lc_mul_plain(lc_ctx *ctx, const uint64_t *ct_dev, const uint64_t *pt_dev, uint64_t *out_dev, size_t count,
+                 void *stream);
+/* ServerUpdate (Algorithm 1): out[k] = sum_i ct_i[k] * mask_i, client_cts
+ * [n][len][2][n_q][N], masks [n][n_q][N] (NTT domain), out [len][2][n_q][N]. */
+int lc_masked_sum(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const uint64_t *masks_dev,
+                  uint64_t *out_dev, void *stream);
+
+/* ---- the pairwise-distance pipeline (Algorithm 1, Server Executes) ------- */
+
+/* Lazy triples only: for pairs i < j in row-major order, sum over k < len of
+ * (ct_i[k] - ct_j[k])^2 as triples.  triples [P][3][n_q][N], P = n(n-1)/2.
+ * len <= 4096. */
+int lc_pair_triples(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, uint64_t *triples_dev,
+                    void *stream);
+/* Full batched pipeline: lazy triples, one relinearization per pair,
+ * rotate-and-sum with `plan`; dist [P][2][n_q][N].  sumdis (may be NULL)
+ * [n][2][n_q][N] gets sum over j != i of Dis[i][j]. */
+int lc_pairwise_sqdist(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const int *plan, int nblocks,
+                       uint64_t *dist_dev, uint64_t *sumdis_dev, void *stream);
+
+/* ---- transforms ------------------------------------------------------------ */
+
+/* In-place negacyclic NTT / inverse NTT of count polynomials of nlimb limbs
+ * each ([count][nlimb][N]); limb l of each uses modulus limb0 + l of the
+ * extended basis (q's then p's). */
+int lc_ntt_fwd(lc_ctx *ctx, uint64_t *polys_dev, size_t count, int nlimb, int limb0, void *stream);
+int lc_ntt_inv(lc_ctx *ctx, uint64_t *polys_dev, size_t count, int nlimb, int limb0, void *stream);
+
+/* ---- memory planning ------------------------------------------------------- */
+
+/* Workspace bytes that lc_pairwise_sqdist needs for n clients. */
+int lc_workspace_query(const lc_ctx *ctx, int n, int len, size_t *bytes);
+/* Caps the workspace the library may hold (0 = no cap); calls that would
+ * need more run in smaller batches, or fail with LC_ENOMEM. */
+int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

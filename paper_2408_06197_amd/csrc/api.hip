@@ -1,0 +1,644 @@
+// The C ABI declared in include/lancelot.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lc_internal.h"
+
+struct lc_ctx {
+    lc::Ctx c;
+};
+
+namespace lc {
+
+typedef unsigned __int128 u128;
+
+int fail(Ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(Ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, LC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+u64 *ws_get(Ctx *c, int slot, size_t bytes)
+{
+    if (c->slot_bytes[slot] >= bytes && c->slot[slot]) return (u64 *)c->slot[slot];
+    if (c->slot[slot]) {
+        hipDeviceSynchronize();
+        hipFree(c->slot[slot]);
+        c->slot[slot] = nullptr;
+        c->slot_bytes[slot] = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        hipGetLastError();
+        c->err = "workspace allocation of " + std::to_string(bytes) + " bytes failed";
+        return nullptr;
+    }
+    c->slot[slot] = p;
+    c->slot_bytes[slot] = bytes;
+    return (u64 *)p;
+}
+
+static std::vector<u64> shoup_host(const std::vector<u64> &v, const std::vector<u64> &mod, int nlimb, u64 N)
+{
+    std::vector<u64> out(v.size());
+    for (size_t i = 0; i < v.size(); i++) {
+        int l = (int)((i / N) % (u64)nlimb);
+        out[i] = (u64)(((u128)v[i] << 64) / mod[l]);
+    }
+    return out;
+}
+
+static int upload_shoup(Ctx *c, const u64 *dev, u64 *dev_sh, int nlimb, u64 count)
+{
+    size_t n = (size_t)count * nlimb * c->N;
+    std::vector<u64> h(n);
+    LC_HIP(c, hipMemcpy(h.data(), dev, n * 8, hipMemcpyDeviceToHost));
+    std::vector<u64> sh = shoup_host(h, c->mod, nlimb, c->N);
+    LC_HIP(c, hipMemcpy(dev_sh, sh.data(), n * 8, hipMemcpyHostToDevice));
+    return LC_OK;
+}
+
+// Key-switching key from s to target t (NTT domain over all ne limbs).
+static int gen_ksk(Ctx *c, u64 seed, u64 key_id, const u64 *t_ntt, u64 *ksk)
+{
+    const int ne = c->ne, nq = c->nq, alpha = c->alpha;
+    const u64 N = c->N, NE = (u64)ne * N;
+    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8);
+    if (!tmp) return LC_ENOMEM;
+    u64 *e_ntt = tmp;
+    i64 *e_coef = (i64 *)(tmp + NE);
+    u64 *gadget = tmp + NE + N;
+    std::vector<u64> pmod(nq);
+    LC_HIP(c, hipMemcpy(pmod.data(), c->dp.pmod, nq * 8, hipMemcpyDeviceToHost));
+    int rc;
+    for (int d = 0; d < c->dnum; d++) {
+        u64 *k0 = ksk + (u64)d * 2 * NE, *k1 = k0 + NE;
+        if ((rc = launch_uniform_limbs(c, seed, 7, (key_id << 32) | ((u64)d << 16), k1, ne, 0))) return rc;
+        if ((rc = launch_gaussian(c, seed, 8, (key_id << 32) | (u64)d, e_coef, 0))) return rc;
+        if ((rc = launch_signed_to_limbs(c, e_coef, e_ntt, ne, 1, 0))) return rc;
+        if ((rc = launch_ntt_fwd(c, PolyBatch{e_ntt, 1, ne, (u64)ne, 0, 0}, 0))) return rc;
+        std::vector<u64> g(ne, 0);
+        for (int l = 0; l < nq; l++)
+            if (l / alpha == d) g[l] = pmod[l];
+        LC_HIP(c, hipMemcpy(gadget, g.data(), ne * 8, hipMemcpyHostToDevice));
+        if ((rc = launch_keycombine(c, k1, e_ntt, c->sk_ntt, t_ntt, gadget, k0, k1, ne, 0))) return rc;
+    }
+    LC_HIP(c, hipDeviceSynchronize());
+    return LC_OK;
+}
+
+static Ctx *C(lc_ctx *x) { return x ? &x->c : nullptr; }
+static const Ctx *C(const lc_ctx *x) { return x ? &x->c : nullptr; }
+
+static bool set_device(Ctx *c)
+{
+    return hipSetDevice(c->device) == hipSuccess;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+#define CHECK_CTX(x)                                                              \
+    if (!(x)) return LC_EINVAL;                                                   \
+    Ctx *c = C(x);                                                                \
+    if (c->device < 0) return fail(c, LC_EUNSUP, "host-only context (device -1)"); \
+    if (!set_device(c)) return fail(c, LC_EHIP, "hipSetDevice failed");
+
+extern "C" {
+
+int lc_ctx_create(const lc_params *prm, int device, int role, lc_ctx **out)
+{
+    if (!out) return LC_EINVAL;
+    *out = nullptr;
+    if (role != LC_ROLE_SERVER && role != LC_ROLE_KGC) return LC_EINVAL;
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return LC_EHIP;
+    } else if (device != -1) {
+        return LC_EINVAL;
+    }
+    lc_ctx *x = new (std::nothrow) lc_ctx();
+    if (!x) return LC_ENOMEM;
+    x->c.device = device;
+    x->c.role = role;
+    if (device >= 0 && hipSetDevice(device) != hipSuccess) {
+        delete x;
+        return LC_EHIP;
+    }
+    int rc = build_params(&x->c, prm);
+    if (rc) {
+        lc_ctx_destroy(x);
+        return rc;
+    }
+    *out = x;
+    return LC_OK;
+}
+
+int lc_ctx_destroy(lc_ctx *x)
+{
+    if (!x) return LC_EINVAL;
+    Ctx *c = &x->c;
+    if (c->device >= 0) {
+        hipSetDevice(c->device);
+        hipDeviceSynchronize();
+        for (void *p : c->allocs) hipFree(p);
+        for (int i = 0; i < 8; i++)
+            if (c->slot[i]) hipFree(c->slot[i]);
+    }
+    delete x;
+    return LC_OK;
+}
+
+const char *lc_last_error(const lc_ctx *x) { return x ? x->c.err.c_str() : "null context"; }
+
+int lc_ctx_moduli(const lc_ctx *x, uint64_t *out)
+{
+    if (!x || !out) return LC_EINVAL;
+    std::memcpy(out, x->c.mod.data(), x->c.mod.size() * 8);
+    return LC_OK;
+}
+
+int lc_ctx_info(const lc_ctx *x, int *log_n, int *n_q, int *n_p, int *dnum)
+{
+    if (!x) return LC_EINVAL;
+    if (log_n) *log_n = x->c.log_n;
+    if (n_q) *n_q = x->c.nq;
+    if (n_p) *n_p = x->c.np;
+    if (dnum) *dnum = x->c.dnum;
+    return LC_OK;
+}
+
+int lc_sync(lc_ctx *x, void *stream)
+{
+    CHECK_CTX(x);
+    LC_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+    LC_HIP(c, hipGetLastError());
+    return LC_OK;
+}
+
+int lc_ctx_device_bytes(const lc_ctx *x, size_t *bytes)
+{
+    if (!x || !bytes) return LC_EINVAL;
+    size_t b = x->c.table_bytes + x->c.key_bytes;
+    for (int i = 0; i < 8; i++) b += x->c.slot_bytes[i];
+    *bytes = b;
+    return LC_OK;
+}
+
+// ---- keys --------------------------------------------------------------------
+
+int lc_keygen(lc_ctx *x, uint64_t seed)
+{
+    CHECK_CTX(x);
+    if (c->role != LC_ROLE_KGC) return fail(c, LC_EKEY, "key generation needs a KGC-role context");
+    const int ne = c->ne, nq = c->nq;
+    const u64 N = c->N, NE = (u64)ne * N, S = (u64)nq * N;
+    if (!c->sk_coeff) {
+        c->sk_coeff = (i64 *)dev_alloc(c, N * 8);
+        c->sk_ntt = (u64 *)dev_alloc(c, NE * 8);
+        c->sk_ntt_sh = (u64 *)dev_alloc(c, NE * 8);
+        c->sk2_ntt = (u64 *)dev_alloc(c, S * 8);
+        c->sk2_ntt_sh = (u64 *)dev_alloc(c, S * 8);
+        c->pk = (u64 *)dev_alloc(c, 2 * S * 8);
+        c->pk_sh = (u64 *)dev_alloc(c, 2 * S * 8);
+        c->rlk = (u64 *)dev_alloc(c, (u64)c->dnum * 2 * NE * 8);
+        if (!c->sk_coeff || !c->sk_ntt || !c->sk_ntt_sh || !c->sk2_ntt || !c->sk2_ntt_sh || !c->pk || !c->pk_sh ||
+            !c->rlk)
+            return fail(c, LC_ENOMEM, "key allocation failed");
+        c->key_bytes += (N + 2 * NE + 2 * S + 4 * S + (u64)c->dnum * 2 * NE) * 8;
+    }
+    int rc;
+    // secret
+    if ((rc = launch_sample_ternary(c, seed, 1, 0, c->sk_coeff, 0))) return rc;
+    if ((rc = launch_signed_to_limbs(c, c->sk_coeff, c->sk_ntt, ne, 1, 0))) return rc;
+    if ((rc = launch_ntt_fwd(c, PolyBatch{c->sk_ntt, 1, ne, (u64)ne, 0, 0}, 0))) return rc;
+    if ((rc = launch_pointwise_sq(c, c->sk_ntt, c->sk2_ntt, nq, 0))) return rc;
+    LC_HIP(c, hipDeviceSynchronize());
+    if ((rc = upload_shoup(c, c->sk_ntt, c->sk_ntt_sh, ne, 1))) return rc;
+    if ((rc = upload_shoup(c, c->sk2_ntt, c->sk2_ntt_sh, nq, 1))) return rc;
+    // public key: a uniform (NTT domain), e Gaussian
+    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8);
+    if (!tmp) return LC_ENOMEM;
+    u64 *e_ntt = tmp;
+    i64 *e_coef = (i64 *)(tmp + NE);
+    if ((rc = launch_uniform_limbs(c, seed, 2, 0, c->pk + S, nq, 0))) return rc;
+    if ((rc = launch_gaussian(c, seed, 3, 0, e_coef, 0))) return rc;
+    if ((rc = launch_signed_to_limbs(c, e_coef, e_ntt, nq, 1, 0))) return rc;
+    if ((rc = launch_ntt_fwd(c, PolyBatch{e_ntt, 1, nq, (u64)nq, 0, 0}, 0))) return rc;
+    if ((rc = launch_keycombine(c, c->pk + S, e_ntt, c->sk_ntt, nullptr, nullptr, c->pk, c->pk + S, nq, 0))) return rc;
+    LC_HIP(c, hipDeviceSynchronize());
+    if ((rc = upload_shoup(c, c->pk, c->pk_sh, nq, 2))) return rc;
+    // relinearization key: target s^2 over all ne limbs
+    u64 *t = ws_get(c, WS_TMP, NE * 8);
+    if (!t) return LC_ENOMEM;
+    if ((rc = launch_pointwise_sq(c, c->sk_ntt, t, ne, 0))) return rc;
+    if ((rc = gen_ksk(c, seed, 0, t, c->rlk))) return rc;
+    // rotation keys made before a re-keygen are stale
+    c->rot.clear();
+    return LC_OK;
+}
+
+int lc_keygen_rotation(lc_ctx *x, uint64_t seed, const int *steps, int nsteps)
+{
+    CHECK_CTX(x);
+    if (c->role != LC_ROLE_KGC) return fail(c, LC_EKEY, "key generation needs a KGC-role context");
+    if (!c->sk_ntt) return fail(c, LC_EKEY, "call lc_keygen first");
+    if (nsteps < 0 || (nsteps && !steps)) return fail(c, LC_EINVAL, "bad steps");
+    const u64 NE = (u64)c->ne * c->N;
+    u64 *t = ws_get(c, WS_TMP, NE * 8);
+    if (!t) return LC_ENOMEM;
+    for (int i = 0; i < nsteps; i++) {
+        u64 g = galois_of_step(c->log_n, steps[i]);
+        if (g == 1 || c->rot.count(g)) continue;
+        u32 *perm = get_perm(c, g);
+        u64 *k = (u64 *)dev_alloc(c, (u64)c->dnum * 2 * NE * 8);
+        if (!perm || !k) return fail(c, LC_ENOMEM, "rotation key allocation failed");
+        c->key_bytes += (u64)c->dnum * 2 * NE * 8;
+        int rc;
+        if ((rc = launch_permute(c, c->sk_ntt, t, perm, c->ne, 0))) return rc;
+        if ((rc = gen_ksk(c, seed, g, t, k))) return rc;
+        c->rot[g] = RotKey{k, perm, g};
+    }
+    return LC_OK;
+}
+
+int lc_keys_share(const lc_ctx *xs, lc_ctx *xd)
+{
+    if (!xs || !xd) return LC_EINVAL;
+    const Ctx *s = &xs->c;
+    Ctx *c = &xd->c;
+    if (s->mod != c->mod || s->log_n != c->log_n || s->device != c->device)
+        return fail(c, LC_EINVAL, "contexts differ in parameters or device");
+    if (!s->pk) return fail(c, LC_EKEY, "source has no keys");
+    if (!set_device(c)) return LC_EHIP;
+    const u64 S = (u64)c->nq * c->N, NE = (u64)c->ne * c->N, K = (u64)c->dnum * 2 * NE;
+    if (!c->pk) {
+        c->pk = (u64 *)dev_alloc(c, 2 * S * 8);
+        c->pk_sh = (u64 *)dev_alloc(c, 2 * S * 8);
+        c->rlk = (u64 *)dev_alloc(c, K * 8);
+        if (!c->pk || !c->pk_sh || !c->rlk) return fail(c, LC_ENOMEM, "key allocation failed");
+        c->key_bytes += (4 * S + K) * 8;
+    }
+    LC_HIP(c, hipMemcpy(c->pk, s->pk, 2 * S * 8, hipMemcpyDeviceToDevice));
+    LC_HIP(c, hipMemcpy(c->pk_sh, s->pk_sh, 2 * S * 8, hipMemcpyDeviceToDevice));
+    LC_HIP(c, hipMemcpy(c->rlk, s->rlk, K * 8, hipMemcpyDeviceToDevice));
+    for (auto &kv : s->rot) {
+        if (c->rot.count(kv.first)) continue;
+        u64 *k = (u64 *)dev_alloc(c, K * 8);
+        u32 *perm = get_perm(c, kv.first);
+        if (!k || !perm) return fail(c, LC_ENOMEM, "key allocation failed");
+        c->key_bytes += K * 8;
+        LC_HIP(c, hipMemcpy(k, kv.second.ksk, K * 8, hipMemcpyDeviceToDevice));
+        c->rot[kv.first] = RotKey{k, perm, kv.first};
+    }
+    return LC_OK;
+}
+
+int lc_secret_export(const lc_ctx *x, int64_t *s_host)
+{
+    if (!x || !s_host) return LC_EINVAL;
+    Ctx *c = const_cast<Ctx *>(&x->c);
+    if (c->role != LC_ROLE_KGC || !c->sk_coeff) return fail(c, LC_EKEY, "no secret key in this context");
+    if (!set_device(c)) return LC_EHIP;
+    LC_HIP(c, hipMemcpy(s_host, c->sk_coeff, c->N * 8, hipMemcpyDeviceToHost));
+    return LC_OK;
+}
+
+int lc_pk_export(const lc_ctx *x, uint64_t *pk_host)
+{
+    if (!x || !pk_host) return LC_EINVAL;
+    Ctx *c = const_cast<Ctx *>(&x->c);
+    if (!c->pk) return fail(c, LC_EKEY, "no public key");
+    if (!set_device(c)) return LC_EHIP;
+    LC_HIP(c, hipMemcpy(pk_host, c->pk, 2 * (u64)c->nq * c->N * 8, hipMemcpyDeviceToHost));
+    return LC_OK;
+}
+
+int lc_ksk_export(const lc_ctx *x, int which, int step, uint64_t *out)
+{
+    if (!x || !out) return LC_EINVAL;
+    Ctx *c = const_cast<Ctx *>(&x->c);
+    if (!set_device(c)) return LC_EHIP;
+    const u64 K = (u64)c->dnum * 2 * c->ne * c->N;
+    const u64 *src = nullptr;
+    if (which == 0) src = c->rlk;
+    else if (which == 1) {
+        auto it = c->rot.find(galois_of_step(c->log_n, step));
+        if (it != c->rot.end()) src = it->second.ksk;
+    } else return fail(c, LC_EINVAL, "which must be 0 or 1");
+    if (!src) return fail(c, LC_EKEY, "key not present");
+    LC_HIP(c, hipMemcpy(out, src, K * 8, hipMemcpyDeviceToHost));
+    return LC_OK;
+}
+
+// ---- encode / decode ------------------------------------------------------------
+
+int lc_encode(const lc_ctx *x, const double *re, const double *im, size_t nslots, double scale, int64_t *m)
+{
+    if (!x || !re || !m) return LC_EINVAL;
+    if (nslots > x->c.N / 2) return LC_EINVAL;
+    encode_host(x->c.log_n, re, im, nslots, scale, m);
+    return LC_OK;
+}
+
+int lc_decode(const lc_ctx *x, const uint64_t *res, double scale, double *re, double *im)
+{
+    if (!x || !res || !re) return LC_EINVAL;
+    const Ctx *c = &x->c;
+    std::vector<u64> q(c->mod.begin(), c->mod.begin() + c->nq);
+    std::vector<double> coeff(c->N);
+    crt_to_double(q, res, c->N, c->N, coeff.data());
+    decode_host(c->log_n, coeff.data(), scale, re, im);
+    return LC_OK;
+}
+
+int lc_crt_to_double(const lc_ctx *x, const uint64_t *res, size_t ncoeff, size_t stride, double *out)
+{
+    if (!x || !res || !out || ncoeff > stride) return LC_EINVAL;
+    const Ctx *c = &x->c;
+    std::vector<u64> q(c->mod.begin(), c->mod.begin() + c->nq);
+    crt_to_double(q, res, ncoeff, stride, out);
+    return LC_OK;
+}
+
+// ---- encryption / decryption -----------------------------------------------------
+
+int lc_encrypt(lc_ctx *x, const int64_t *m, size_t count, uint64_t seed, uint64_t first_object, uint64_t *ct,
+               void *stream)
+{
+    CHECK_CTX(x);
+    if (!c->pk) return fail(c, LC_EKEY, "no public key");
+    if ((!m || !ct) && count) return fail(c, LC_EINVAL, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
+    u64 chunk = std::min<u64>(count, std::max<u64>(1, (1ull << 31) / (3 * S * 8)));
+    u64 *tmp = ws_get(c, WS_ENC, chunk * 3 * S * 8);
+    if (!tmp) return LC_ENOMEM;
+    for (u64 t0 = 0; t0 < count; t0 += chunk) {
+        u64 B = std::min<u64>(chunk, count - t0);
+        int rc;
+        if ((rc = launch_enc_sample(c, m + t0 * c->N, B, seed, first_object + t0, tmp, s))) return rc;
+        if ((rc = launch_ntt_fwd(c, PolyBatch{tmp, B * 3, c->nq, (u64)c->nq, 0, 0}, s))) return rc;
+        if ((rc = launch_enc_combine(c, tmp, B, ct + t0 * 2 * S, s))) return rc;
+    }
+    return LC_OK;
+}
+
+int lc_decrypt(lc_ctx *x, const uint64_t *ct, int ncomp, size_t count, uint64_t *pt, void *stream)
+{
+    CHECK_CTX(x);
+    if (c->role != LC_ROLE_KGC || !c->sk_ntt) return fail(c, LC_EKEY, "decryption needs the secret key (KGC role)");
+    if (ncomp != 2 && ncomp != 3) return fail(c, LC_EINVAL, "ncomp must be 2 or 3");
+    if (!count) return LC_OK;
+    if (!ct || !pt) return fail(c, LC_EINVAL, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = launch_dec_combine(c, ct, ncomp, count, pt, s))) return rc;
+    return launch_ntt_inv(c, PolyBatch{pt, count, c->nq, (u64)c->nq, 0, 0}, s);
+}
+
+// ---- homomorphic operations -------------------------------------------------------
+
+int lc_ct_sub(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count, int ncomp, void *stream)
+{
+    CHECK_CTX(x);
+    if (ncomp < 1 || ncomp > 3) return fail(c, LC_EINVAL, "ncomp must be 1..3");
+    if (count && (!a || !b || !out)) return fail(c, LC_EINVAL, "null buffer");
+    return launch_add_sub(c, a, b, out, count, ncomp, 1, (hipStream_t)stream);
+}
+
+int lc_ct_add(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count, int ncomp, void *stream)
+{
+    CHECK_CTX(x);
+    if (ncomp < 1 || ncomp > 3) return fail(c, LC_EINVAL, "ncomp must be 1..3");
+    if (count && (!a || !b || !out)) return fail(c, LC_EINVAL, "null buffer");
+    return launch_add_sub(c, a, b, out, count, ncomp, 0, (hipStream_t)stream);
+}
+
+int lc_ct_mul(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out3, size_t count, void *stream)
+{
+    CHECK_CTX(x);
+    if (count && (!a || !b || !out3)) return fail(c, LC_EINVAL, "null buffer");
+    return launch_tensor(c, a, b, out3, count, (hipStream_t)stream);
+}
+
+int lc_ct_square(lc_ctx *x, const uint64_t *a, uint64_t *out3, size_t count, void *stream)
+{
+    CHECK_CTX(x);
+    if (count && (!a || !out3)) return fail(c, LC_EINVAL, "null buffer");
+    return launch_tensor(c, a, nullptr, out3, count, (hipStream_t)stream);
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+int lc_relin(lc_ctx *x, const uint64_t *ct3, uint64_t *ct2, size_t count, void *stream)
+{
+    CHECK_CTX(x);
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    if (!count) return LC_OK;
+    if (!ct3 || !ct2) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    if (overlap(ct3, count * 3 * S * 8, ct2, count * 2 * S * 8))
+        return fail(c, LC_EINVAL, "lc_relin output must not overlap its input");
+    KsGroup g{};
+    g.keys[0] = c->rlk;
+    g.n = 1;
+    g.base = ct3;
+    g.base_stride = 3 * S;
+    g.out = ct2;
+    g.out_stride = 2 * S;
+    return keyswitch_hoisted(c, ct3 + 2 * S, 3 * S, count, &g, 1, (hipStream_t)stream);
+}
+
+int lc_rotate_hoisted(lc_ctx *x, const uint64_t *ct, size_t count, const int *steps, int nsteps, uint64_t *outs,
+                      void *stream)
+{
+    CHECK_CTX(x);
+    if (nsteps < 1 || nsteps > 64 || !steps) return fail(c, LC_EINVAL, "1..64 steps");
+    if (!count) return LC_OK;
+    if (!ct || !outs) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    if (overlap(ct, count * 2 * S * 8, outs, count * nsteps * 2 * S * 8))
+        return fail(c, LC_EINVAL, "output must not overlap the input");
+    std::vector<KsGroup> groups(nsteps);
+    for (int t = 0; t < nsteps; t++) {
+        u64 g = galois_of_step(c->log_n, steps[t]);
+        auto it = c->rot.find(g);
+        if (it == c->rot.end()) return fail(c, LC_EKEY, "no rotation key for step " + std::to_string(steps[t]));
+        KsGroup &G = groups[t];
+        G = KsGroup{};
+        G.keys[0] = it->second.ksk;
+        G.perms[0] = it->second.perm;
+        G.n = 1;
+        G.c0src = ct;
+        G.c0_stride = 2 * S;
+        G.out = outs + (u64)t * 2 * S;
+        G.out_stride = (u64)nsteps * 2 * S;
+    }
+    return keyswitch_hoisted(c, ct + S, 2 * S, count, groups.data(), nsteps, (hipStream_t)stream);
+}
+
+int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nblocks, void *stream)
+{
+    CHECK_CTX(x);
+    std::vector<int> pl;
+    if (!plan) pl.assign(c->log_n - 1, 1);
+    else pl.assign(plan, plan + nblocks);
+    int total = 0;
+    for (int k : pl) {
+        if (k < 1 || k > 3) return fail(c, LC_EINVAL, "plan blocks must have 1..3 levels");
+        total += k;
+    }
+    if (total != c->log_n - 1) return fail(c, LC_EINVAL, "plan levels must sum to log_n - 1");
+    if (!count) return LC_OK;
+    if (!ct) return fail(c, LC_EINVAL, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
+    // keys of every block, checked up front
+    std::vector<KsGroup> blocks;
+    int j0 = 0;
+    for (int k : pl) {
+        KsGroup G{};
+        G.n = (1 << k) - 1;
+        for (int t = 1; t <= G.n; t++) {
+            u64 g = galois_of_step(c->log_n, (long long)t << j0);
+            auto it = c->rot.find(g);
+            if (it == c->rot.end())
+                return fail(c, LC_EKEY, "no rotation key for step " + std::to_string((long long)t << j0));
+            G.keys[t - 1] = it->second.ksk;
+            G.perms[t - 1] = it->second.perm;
+        }
+        blocks.push_back(G);
+        j0 += k;
+    }
+    u64 chunk = std::min<u64>(count, 64);
+    u64 *other = ws_get(c, WS_ROT, chunk * 2 * S * 8);
+    if (!other) return LC_ENOMEM;
+    for (u64 b0 = 0; b0 < count; b0 += chunk) {
+        u64 B = std::min<u64>(chunk, count - b0);
+        u64 *y = ct + b0 * 2 * S, *z = other;
+        for (KsGroup G : blocks) {
+            G.base = y;
+            G.base_stride = 2 * S;
+            G.c0src = y;
+            G.c0_stride = 2 * S;
+            G.out = z;
+            G.out_stride = 2 * S;
+            int rc = keyswitch_hoisted(c, y + S, 2 * S, B, &G, 1, s);
+            if (rc) return rc;
+            std::swap(y, z);
+        }
+        if (y != ct + b0 * 2 * S) {
+            int rc = launch_copy(c, y, ct + b0 * 2 * S, B * 2 * S, s);
+            if (rc) return rc;
+        }
+    }
+    return LC_OK;
+}
+
+int lc_mul_plain(lc_ctx *x, const uint64_t *ct, const uint64_t *pt, uint64_t *out, size_t count, void *stream)
+{
+    CHECK_CTX(x);
+    if (count && (!ct || !pt || !out)) return fail(c, LC_EINVAL, "null buffer");
+    return launch_mul_plain(c, ct, pt, out, count, (hipStream_t)stream);
+}
+
+int lc_masked_sum(lc_ctx *x, const uint64_t *cts, int n, int len, const uint64_t *masks, uint64_t *out, void *stream)
+{
+    CHECK_CTX(x);
+    if (n < 1 || n > 4096 || len < 1) return fail(c, LC_EINVAL, "need 1 <= n <= 4096 and len >= 1");
+    if (!cts || !masks || !out) return fail(c, LC_EINVAL, "null buffer");
+    return launch_masked_sum(c, cts, n, len, masks, out, (hipStream_t)stream);
+}
+
+int lc_pair_triples(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t *triples, void *stream)
+{
+    CHECK_CTX(x);
+    if (!cts || !triples) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, (hipStream_t)stream);
+}
+
+int lc_pairwise_sqdist(lc_ctx *x, const uint64_t *cts, int n, int len, const int *plan, int nblocks, uint64_t *dist,
+                       uint64_t *sumdis, void *stream)
+{
+    CHECK_CTX(x);
+    if (!cts || !dist) return fail(c, LC_EINVAL, "null buffer");
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    if (n < 2 || n > 64) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
+    const u64 P = (u64)n * (n - 1) / 2;
+    u64 *d2 = ws_get(c, WS_PIPE, P * S * 8);
+    if (!d2) return LC_ENOMEM;
+    int rc;
+    if ((rc = launch_pair_triples(c, cts, n, len, dist, 2 * S, d2, S, s))) return rc;
+    KsGroup g{};
+    g.keys[0] = c->rlk;
+    g.n = 1;
+    g.base = dist;
+    g.base_stride = 2 * S;
+    g.out = dist;
+    g.out_stride = 2 * S;
+    if ((rc = keyswitch_hoisted(c, d2, S, P, &g, 1, s))) return rc;
+    if ((rc = lc_rotate_sum(x, dist, P, plan, nblocks, stream))) return rc;
+    if (sumdis) return launch_sumdis(c, dist, n, sumdis, s);
+    return LC_OK;
+}
+
+int lc_ntt_fwd(lc_ctx *x, uint64_t *polys, size_t count, int nlimb, int limb0, void *stream)
+{
+    CHECK_CTX(x);
+    if (nlimb < 1 || limb0 < 0 || limb0 + nlimb > c->ne) return fail(c, LC_EINVAL, "limb range outside the basis");
+    if (count && !polys) return fail(c, LC_EINVAL, "null buffer");
+    return launch_ntt_fwd(c, PolyBatch{polys, count, nlimb, (u64)nlimb, limb0, 0}, (hipStream_t)stream);
+}
+
+int lc_ntt_inv(lc_ctx *x, uint64_t *polys, size_t count, int nlimb, int limb0, void *stream)
+{
+    CHECK_CTX(x);
+    if (nlimb < 1 || limb0 < 0 || limb0 + nlimb > c->ne) return fail(c, LC_EINVAL, "limb range outside the basis");
+    if (count && !polys) return fail(c, LC_EINVAL, "null buffer");
+    return launch_ntt_inv(c, PolyBatch{polys, count, nlimb, (u64)nlimb, limb0, 0}, (hipStream_t)stream);
+}
+
+int lc_gaussian_table(const lc_ctx *x, uint64_t *out38)
+{
+    if (!x || !out38) return LC_EINVAL;
+    std::memcpy(out38, x->c.cdt_host.data(), 38 * 8);
+    return LC_OK;
+}
+
+int lc_workspace_query(const lc_ctx *x, int n, int len, size_t *bytes)
+{
+    if (!x || !bytes || n < 2) return LC_EINVAL;
+    (void)len;
+    const Ctx *c = &x->c;
+    const u64 S = (u64)c->nq * c->N, P = (u64)n * (n - 1) / 2;
+    u64 chunk = std::min<u64>(P, 64);
+    *bytes = (P * S + chunk * ks_words_per_ct(c) + chunk * 2 * S) * 8;
+    return LC_OK;
+}
+
+int lc_set_workspace_limit(lc_ctx *x, size_t bytes)
+{
+    if (!x) return LC_EINVAL;
+    x->c.ws_limit = bytes;
+    return LC_OK;
+}
+
+}  // extern "C"

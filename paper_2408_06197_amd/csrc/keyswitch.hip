@@ -1,0 +1,208 @@
+// Hybrid key switching (Methods, Dynamic Hoisting: RNS decompose, ModUp,
+// switch key, ModDown), batched over ciphertexts and hoisted over keys.
+//
+// For each input x (NTT domain, n_q limbs):
+//   1. x^ = iNTT(x);
+//   2. digit d (limbs D_d, alpha of them): for every limb l outside D_d,
+//      X_d[l] = sum_{a in D_d} [x^_a (Q_d/q_a)^-1]_{q_a} (Q_d/q_a) mod m_l
+//      (fast base conversion, no overflow correction); NTT of those limbs.
+//      Limbs inside D_d reuse x itself;
+//   3. acc_k = sum_t sum_d phi_t(X_d) * key_{t,d,k} over the n_q + n_p limbs,
+//      phi_t a permutation in the NTT domain (identity for relinearization);
+//      one raise serves every key t: hoisting;
+//   4. ModDown: (acc_Q - BConv_{P->Q}(iNTT(acc_P)))^ * P^-1 mod q_l;
+//   5. out0 = base0 + sum_t phi_t(c0src) + ModDown(acc_0), out1 = base1 +
+//      ModDown(acc_1).
+#include "lc_internal.h"
+
+namespace lc {
+
+constexpr int KS_THREADS = 256;
+
+static inline u32 blocks_for(u64 n) { return (u32)((n + KS_THREADS - 1) / KS_THREADS); }
+
+// count blocks of `words` from src (stride sstride) to dst (stride dstride)
+__global__ void __launch_bounds__(KS_THREADS)
+strided_copy_kernel(const u64 *src, u64 sstride, u64 *dst, u64 dstride, u64 words, u64 count)
+{
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= words * count) return;
+    u64 b = e / words, r = e % words;
+    dst[b * dstride + r] = src[b * sstride + r];
+}
+
+// raised[b][d][l][j] for l outside digit d, coefficient domain.
+__global__ void __launch_bounds__(KS_THREADS)
+modup_bconv_kernel(DevParams dp, const u64 *xhat, u64 *raised, u64 count)
+{
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over count * dnum * N
+    if (e >= count * dp.dnum * (u64)dp.N) return;
+    u64 j = e & (dp.N - 1);
+    u64 bd = e >> dp.log_n;
+    int d = (int)(bd % dp.dnum);
+    u64 b = bd / dp.dnum;
+    int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
+    u64 y[MAX_NP];
+    for (int a = 0; a < na; a++) {
+        const ModConst &mc = dp.mc[a0 + a];
+        u64 v = xhat[(b * dp.nq + a0 + a) * dp.N + j];
+        y[a] = mul_shoup(v, dp.up_inv[d * dp.alpha + a], dp.up_inv_sh[d * dp.alpha + a], mc.m);
+    }
+    u64 *out = raised + (b * dp.dnum + d) * (u64)dp.ne * dp.N + j;
+    for (int l = 0; l < dp.ne; l++) {
+        if (l >= a0 && l < a0 + na) continue;
+        Split3 s;
+        split_zero(s);
+        const u64 *fac = dp.up_fac + (u64)d * dp.alpha * dp.ne + l;
+        for (int a = 0; a < na; a++) split_mac(s, y[a], fac[(u64)a * dp.ne]);
+        out[(u64)l * dp.N] = reduce_split(s, dp.mc[l]);
+    }
+}
+
+struct KeySet {
+    const u64 *key[8];
+    const u32 *perm[8];  // NULL = identity
+    int n;
+};
+
+// acc[b][k][l][j] = sum_t sum_d X_d[l][perm_t(j)] key_t[d][k][l][j]
+__global__ void __launch_bounds__(KS_THREADS)
+mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, u64 *acc, u64 count)
+{
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over ne * N (one ciphertext per blockIdx.y)
+    u64 b = blockIdx.y;
+    if (e >= (u64)dp.ne * dp.N || b >= count) return;
+    int l = (int)(e >> dp.log_n);
+    u64 j = e & (dp.N - 1);
+    const u64 NE = (u64)dp.ne * dp.N;
+    Split3 s0, s1;
+    split_zero(s0);
+    split_zero(s1);
+    for (int t = 0; t < ks.n; t++) {
+        u64 src = ks.perm[t] ? ks.perm[t][j] : j;
+        const u64 *key = ks.key[t];
+        for (int d = 0; d < dp.dnum; d++) {
+            bool own = l < dp.nq && l / dp.alpha == d;
+            u64 v = own ? x[b * x_stride + (u64)l * dp.N + src]
+                        : raised[((b * dp.dnum + d) * dp.ne + l) * (u64)dp.N + src];
+            split_mac(s0, v, key[((u64)d * 2) * NE + e]);
+            split_mac(s1, v, key[((u64)d * 2 + 1) * NE + e]);
+        }
+    }
+    const ModConst &mc = dp.mc[l];
+    acc[(b * 2) * NE + e] = reduce_split(s0, mc);
+    acc[(b * 2 + 1) * NE + e] = reduce_split(s1, mc);
+}
+
+// v[b][k][l][j] = BConv_{P->Q} of the (coefficient-domain) P limbs of acc.
+__global__ void __launch_bounds__(KS_THREADS)
+moddown_bconv_kernel(DevParams dp, const u64 *acc, u64 *v, u64 count)
+{
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over count * 2 * N
+    if (e >= count * 2 * (u64)dp.N) return;
+    u64 j = e & (dp.N - 1), bk = e >> dp.log_n;
+    const u64 *A = acc + bk * (u64)dp.ne * dp.N;
+    u64 y[MAX_NP];
+    for (int k = 0; k < dp.np; k++) {
+        const ModConst &mc = dp.mc[dp.nq + k];
+        y[k] = mul_shoup(A[(u64)(dp.nq + k) * dp.N + j], dp.dn_inv[k], dp.dn_inv_sh[k], mc.m);
+    }
+    u64 *out = v + bk * (u64)dp.nq * dp.N + j;
+    for (int l = 0; l < dp.nq; l++) {
+        Split3 s;
+        split_zero(s);
+        for (int k = 0; k < dp.np; k++) split_mac(s, y[k], dp.dn_fac[(u64)k * dp.nq + l]);
+        out[(u64)l * dp.N] = reduce_split(s, dp.mc[l]);
+    }
+}
+
+// out0 = base0 + sum_t phi_t(c0src) + (acc0_Q - v0) P^-1, out1 = base1 + (acc1_Q - v1) P^-1
+__global__ void __launch_bounds__(KS_THREADS)
+ks_combine_kernel(DevParams dp, const u64 *acc, const u64 *v, const u64 *base, u64 base_stride, const u64 *c0src,
+                  u64 c0_stride, KeySet ks, u64 *out, u64 out_stride, u64 count)
+{
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over nq * N
+    u64 b = blockIdx.y;
+    const u64 S = (u64)dp.nq * dp.N;
+    if (e >= S || b >= count) return;
+    int l = (int)(e >> dp.log_n);
+    u64 j = e & (dp.N - 1);
+    u64 q = dp.mc[l].m, pi = dp.pinv[l], pish = dp.pinv_sh[l];
+    const u64 NE = (u64)dp.ne * dp.N;
+    u64 r0 = mul_shoup(acc[(b * 2) * NE + e] + q - v[(b * 2) * S + e], pi, pish, q);
+    u64 r1 = mul_shoup(acc[(b * 2 + 1) * NE + e] + q - v[(b * 2 + 1) * S + e], pi, pish, q);
+    if (base) {
+        r0 = add_mod(r0, base[b * base_stride + e], q);
+        r1 = add_mod(r1, base[b * base_stride + S + e], q);
+    }
+    if (c0src) {
+        for (int t = 0; t < ks.n; t++) {
+            u64 src = ks.perm[t] ? ks.perm[t][j] : j;
+            r0 = add_mod(r0, c0src[b * c0_stride + (u64)l * dp.N + src], q);
+        }
+    }
+    out[b * out_stride + e] = r0;
+    out[b * out_stride + S + e] = r1;
+}
+
+u64 ks_words_per_ct(const Ctx *c)
+{
+    return ((u64)c->nq + (u64)c->dnum * c->ne + 2ull * c->ne + 2ull * c->nq) * c->N;
+}
+
+int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
+                      hipStream_t s)
+{
+    const u64 N = c->N;
+    const int nq = c->nq, np = c->np, ne = c->ne, dnum = c->dnum;
+    for (int g = 0; g < ngroups; g++)
+        if (groups[g].n < 1 || groups[g].n > 8) return fail(c, LC_EINVAL, "1..8 keys per hoisted group");
+    const u64 per_ct = ks_words_per_ct(c);
+    u64 chunk = std::min<u64>(count, 64);
+    if (c->ws_limit) chunk = std::max<u64>(1, std::min<u64>(chunk, c->ws_limit / (per_ct * 8)));
+    u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk);
+    if (!ws) return LC_ENOMEM;
+    int rc;
+    for (u64 b0 = 0; b0 < count; b0 += chunk) {
+        u64 B = std::min(chunk, count - b0);
+        u64 *xhat = ws;
+        u64 *raised = xhat + B * nq * N;
+        u64 *acc = raised + B * dnum * ne * N;
+        u64 *v = acc + B * 2 * ne * N;
+        const u64 *xb = x + b0 * x_stride;
+        u64 words = (u64)nq * N;
+        hipLaunchKernelGGL(strided_copy_kernel, dim3(blocks_for(words * B)), dim3(KS_THREADS), 0, s, xb, x_stride,
+                           xhat, words, words, B);
+        LC_HIP(c, hipGetLastError());
+        if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
+        hipLaunchKernelGGL(modup_bconv_kernel, dim3(blocks_for(B * dnum * N)), dim3(KS_THREADS), 0, s, c->dp, xhat,
+                           raised, B);
+        LC_HIP(c, hipGetLastError());
+        if ((rc = launch_ntt_fwd(c, PolyBatch{raised, B * dnum, ne, (u64)ne, 0, 1}, s))) return rc;
+        for (int g = 0; g < ngroups; g++) {
+            const KsGroup &G = groups[g];
+            KeySet ks{};
+            ks.n = G.n;
+            for (int t = 0; t < G.n; t++) {
+                ks.key[t] = G.keys[t];
+                ks.perm[t] = G.perms[t];
+            }
+            hipLaunchKernelGGL(mac_kernel, dim3(blocks_for((u64)ne * N), (u32)B), dim3(KS_THREADS), 0, s, c->dp, xb,
+                               x_stride, raised, ks, acc, B);
+            LC_HIP(c, hipGetLastError());
+            if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
+            hipLaunchKernelGGL(moddown_bconv_kernel, dim3(blocks_for(B * 2 * N)), dim3(KS_THREADS), 0, s, c->dp, acc,
+                               v, B);
+            LC_HIP(c, hipGetLastError());
+            if ((rc = launch_ntt_fwd(c, PolyBatch{v, B * 2, nq, (u64)nq, 0, 0}, s))) return rc;
+            hipLaunchKernelGGL(ks_combine_kernel, dim3(blocks_for((u64)nq * N), (u32)B), dim3(KS_THREADS), 0, s,
+                               c->dp, acc, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride,
+                               G.c0src ? G.c0src + b0 * G.c0_stride : nullptr, G.c0_stride, ks,
+                               G.out + b0 * G.out_stride, G.out_stride, B);
+            LC_HIP(c, hipGetLastError());
+        }
+    }
+    return LC_OK;
+}
+
+}  // namespace lc

@@ -1,0 +1,164 @@
+// Internal declarations shared by the HIP translation units of the engine.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lancelot.h"
+#include "modarith.h"
+
+namespace lc {
+
+typedef int64_t i64;
+
+constexpr int MAX_LIMBS = 56;
+constexpr int MAX_NP = 8;
+
+// Everything a kernel needs to know about the parameter set; passed by value.
+struct DevParams {
+    int log_n;
+    u32 N;
+    int nq, np, ne, alpha, dnum;
+    const ModConst *mc;  // [ne]
+    const u64 *tw, *tw_sh;    // [ne][N]: psi^brev(k) and Shoup companions
+    const u64 *itw, *itw_sh;  // [ne][N]: inverses of the above
+    const u64 *ninv, *ninv_sh;  // [ne]: N^-1 mod m
+    const u64 *up_inv, *up_inv_sh;  // [dnum][alpha]: (Q_d / q_a)^-1 mod q_a
+    const u64 *up_fac;              // [dnum][alpha][ne]: (Q_d / q_a) mod m_l
+    const u64 *dn_inv, *dn_inv_sh;  // [np]: (P / p_k)^-1 mod p_k
+    const u64 *dn_fac;              // [np][nq]: (P / p_k) mod q_l
+    const u64 *pinv, *pinv_sh;      // [nq]: P^-1 mod q_l
+    const u64 *pmod;                // [nq]: P mod q_l (gadget)
+    const u64 *cdt;                 // [38]: Gaussian thresholds
+};
+
+struct RotKey {
+    u64 *ksk = nullptr;    // [dnum][2][ne][N]
+    u32 *perm = nullptr;   // [N]: NTT-domain index map of the automorphism
+    u64 galois = 0;
+};
+
+struct Ctx {
+    int device = 0, role = 0;
+    int log_n = 0;
+    u64 N = 0;
+    int nq = 0, np = 0, ne = 0, alpha = 0, dnum = 0, log_m = 0;
+    std::vector<u64> mod, psi;
+    std::vector<u64> cdt_host;
+    std::string err;
+
+    // device tables (one allocation each, freed at destroy)
+    std::vector<void *> allocs;
+    DevParams dp{};
+
+    // keys
+    u64 *pk = nullptr;       // [2][nq][N]
+    u64 *pk_sh = nullptr;    // Shoup companions of pk
+    u64 *rlk = nullptr;      // [dnum][2][ne][N]
+    std::map<u64, RotKey> rot;   // galois element -> key
+    std::map<u64, u32 *> perms;  // galois element -> permutation (also for keyless uses)
+    i64 *sk_coeff = nullptr;     // [N] (KGC only)
+    u64 *sk_ntt = nullptr;       // [ne][N]
+    u64 *sk_ntt_sh = nullptr;
+    u64 *sk2_ntt = nullptr;      // [nq][N]: s^2
+    u64 *sk2_ntt_sh = nullptr;
+
+    // workspace: independent slots grown on demand
+    void *slot[8] = {};
+    size_t slot_bytes[8] = {};
+    size_t ws_limit = 0;
+    size_t table_bytes = 0, key_bytes = 0;
+};
+
+// error helpers (set ctx->err and return the code)
+int fail(Ctx *c, int code, const std::string &msg);
+int hip_fail(Ctx *c, hipError_t e, const char *what);
+
+#define LC_HIP(ctx, call)                                  \
+    do {                                                   \
+        hipError_t _e = (call);                            \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #call); \
+    } while (0)
+
+// device memory owned by the context
+void *dev_alloc(Ctx *c, size_t bytes);
+enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5 };
+// Pointer to workspace slot `slot` of at least `bytes`; NULL (with ctx->err
+// set) if it cannot be allocated.  Growing a slot waits for the device.
+u64 *ws_get(Ctx *c, int slot, size_t bytes);
+
+// host-side parameter setup (params.cpp)
+int build_params(Ctx *c, const lc_params *prm);
+u64 galois_of_step(int log_n, long long step);
+std::vector<u32> automorphism_perm(int log_n, u64 g);
+u32 *get_perm(Ctx *c, u64 g);
+void cdt_thresholds(u64 out[38]);  // cdt.cpp (quad precision)
+
+// host FP64 encode/decode (encode.cpp)
+void encode_host(int log_n, const double *re, const double *im, size_t nslots, double scale, i64 *m);
+void decode_host(int log_n, const double *coeff, double scale, double *re, double *im);
+void crt_to_double(const std::vector<u64> &q, const u64 *res, size_t ncoeff, size_t stride, double *out);
+
+// ---- kernel launchers ----------------------------------------------------
+// A batch of limb-polynomials for the NTT: polynomial p (0 <= p < count*nlimb)
+// lives at base + ((p / nlimb) * gstride + (p % nlimb)) * N and uses modulus
+// limb0 + p % nlimb.  If skip_own_digit, group g = p / nlimb belongs to digit
+// g % dnum and limbs l < nq with l / alpha == digit are skipped.
+struct PolyBatch {
+    u64 *base;
+    u64 count;     // groups
+    int nlimb;
+    u64 gstride;   // in polynomials
+    int limb0;
+    int skip_own_digit;
+};
+int launch_ntt_fwd(Ctx *c, const PolyBatch &b, hipStream_t s);
+int launch_ntt_inv(Ctx *c, const PolyBatch &b, hipStream_t s);
+
+// elementwise (ops.hip)
+int launch_add_sub(Ctx *c, const u64 *a, const u64 *b, u64 *out, u64 count, int ncomp, int sub, hipStream_t s);
+int launch_tensor(Ctx *c, const u64 *a, const u64 *b, u64 *out3, u64 count, hipStream_t s);  // b NULL: square
+int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, hipStream_t s);
+int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s);
+int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
+                        hipStream_t s);
+int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s);
+int launch_copy(Ctx *c, const u64 *src, u64 *dst, u64 words, hipStream_t s);
+
+// keys / rng (rng.hip)
+int launch_sample_ternary(Ctx *c, u64 seed, u64 domain, u64 object, i64 *out, hipStream_t s);
+int launch_signed_to_limbs(Ctx *c, const i64 *in, u64 *out, int nlimb, u64 count, hipStream_t s);
+int launch_uniform_limbs(Ctx *c, u64 seed, u64 domain, u64 obj_base, u64 *out, int nlimb, hipStream_t s);
+int launch_gaussian(Ctx *c, u64 seed, u64 domain, u64 object, i64 *out, hipStream_t s);
+int launch_keycombine(Ctx *c, const u64 *a, const u64 *e, const u64 *s_ntt, const u64 *t_ntt, const u64 *gadget,
+                      u64 *k0, u64 *k1, int nlimb, hipStream_t s);
+int launch_pointwise_sq(Ctx *c, const u64 *a, u64 *out, int nlimb, hipStream_t s);
+int launch_permute(Ctx *c, const u64 *in, u64 *out, const u32 *perm, u64 npoly, hipStream_t s);
+int launch_enc_sample(Ctx *c, const i64 *m, u64 count, u64 seed, u64 first_object, u64 *tmp, hipStream_t s);
+int launch_enc_combine(Ctx *c, const u64 *tmp, u64 count, u64 *ct, hipStream_t s);
+int launch_dec_combine(Ctx *c, const u64 *ct, int ncomp, u64 count, u64 *out, hipStream_t s);
+
+// key switching (keyswitch.hip)
+// One output of a hoisted key switch: the key products of all keys in the
+// group are summed in PQ before a single ModDown.
+struct KsGroup {
+    const u64 *keys[8];
+    const u32 *perms[8];  // NULL = identity
+    int n;
+    const u64 *base;      // optional [2][nq][N] added to the output (stride per ct)
+    u64 base_stride;
+    const u64 *c0src;     // optional: sum_t phi_t(c0src) added to component 0
+    u64 c0_stride;
+    u64 *out;
+    u64 out_stride;
+};
+// Raises each x (stride x_stride, nq limbs, NTT domain) once and evaluates
+// every group on it.
+int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
+                      hipStream_t s);
+u64 ks_words_per_ct(const Ctx *c);
+
+}  // namespace lc

@@ -1,0 +1,355 @@
+"""Thin ctypes binding of liblancelot.so (the C ABI in include/lancelot.h).
+
+Argument marshalling only: every step of the distance path runs in the HIP
+library.  Device buffers are torch tensors on the context's device, of dtype
+int64 (residues are < 2^50, so the bits equal the ABI's uint64) or uint64;
+streams are torch's current stream unless one is passed.  If the library has
+not been built this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblancelot.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lancelot.h")
+
+LC_OK, LC_EINVAL, LC_ENOMEM, LC_EKEY, LC_EHIP, LC_EUNSUP = 0, -1, -2, -3, -4, -5
+ROLE_SERVER, ROLE_KGC = 0, 1
+
+_c = ctypes
+VP = _c.c_void_p
+U64 = _c.c_uint64
+PU64 = _c.POINTER(_c.c_uint64)
+PI64 = _c.POINTER(_c.c_int64)
+PINT = _c.POINTER(_c.c_int)
+PD = _c.POINTER(_c.c_double)
+SZ = _c.c_size_t
+INT = _c.c_int
+
+
+class LcParams(_c.Structure):
+    _fields_ = [("log_n", INT), ("n_q", INT), ("n_p", INT), ("q_bits", PINT), ("p_bits", PINT), ("log_m", INT)]
+
+
+_SIGS = {
+    "lc_ctx_create": [_c.POINTER(LcParams), INT, INT, _c.POINTER(VP)],
+    "lc_ctx_destroy": [VP],
+    "lc_last_error": [VP],
+    "lc_ctx_moduli": [VP, PU64],
+    "lc_ctx_info": [VP, PINT, PINT, PINT, PINT],
+    "lc_sync": [VP, VP],
+    "lc_ctx_device_bytes": [VP, _c.POINTER(SZ)],
+    "lc_keygen": [VP, U64],
+    "lc_keygen_rotation": [VP, U64, PINT, INT],
+    "lc_keys_share": [VP, VP],
+    "lc_secret_export": [VP, PI64],
+    "lc_pk_export": [VP, PU64],
+    "lc_ksk_export": [VP, INT, INT, PU64],
+    "lc_encode": [VP, PD, PD, SZ, _c.c_double, PI64],
+    "lc_decode": [VP, PU64, _c.c_double, PD, PD],
+    "lc_crt_to_double": [VP, PU64, SZ, SZ, PD],
+    "lc_gaussian_table": [VP, PU64],
+    "lc_encrypt": [VP, VP, SZ, U64, U64, VP, VP],
+    "lc_decrypt": [VP, VP, INT, SZ, VP, VP],
+    "lc_ct_sub": [VP, VP, VP, VP, SZ, INT, VP],
+    "lc_ct_add": [VP, VP, VP, VP, SZ, INT, VP],
+    "lc_ct_mul": [VP, VP, VP, VP, SZ, VP],
+    "lc_ct_square": [VP, VP, VP, SZ, VP],
+    "lc_relin": [VP, VP, VP, SZ, VP],
+    "lc_rotate_hoisted": [VP, VP, SZ, PINT, INT, VP, VP],
+    "lc_rotate_sum": [VP, VP, SZ, PINT, INT, VP],
+    "lc_mul_plain": [VP, VP, VP, VP, SZ, VP],
+    "lc_masked_sum": [VP, VP, INT, INT, VP, VP, VP],
+    "lc_pair_triples": [VP, VP, INT, INT, VP, VP],
+    "lc_pairwise_sqdist": [VP, VP, INT, INT, PINT, INT, VP, VP, VP],
+    "lc_ntt_fwd": [VP, VP, SZ, INT, INT, VP],
+    "lc_ntt_inv": [VP, VP, SZ, INT, INT, VP],
+    "lc_workspace_query": [VP, INT, INT, _c.POINTER(SZ)],
+    "lc_set_workspace_limit": [VP, SZ],
+}
+
+_lib = None
+
+
+class LancelotError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lancelot error {code}: {msg}")
+        self.code = code
+
+
+def header_symbols():
+    """Function names declared in include/lancelot.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lc_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblancelot.so is not built; run `python -m paper_2408_06197_amd.build`")
+        L = _c.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _c.c_char_p if name == "lc_last_error" else INT
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        assert t.is_contiguous(), "tensor must be contiguous"
+        return VP(t.data_ptr())
+    raise TypeError("expected a torch tensor")
+
+
+def _stream(stream):
+    if stream is not None:
+        return VP(stream if isinstance(stream, int) else stream.cuda_stream)
+    import torch
+    return VP(torch.cuda.current_stream().cuda_stream)
+
+
+def _ints(vals):
+    vals = list(vals)
+    return (INT * max(1, len(vals)))(*vals), len(vals)
+
+
+class Context:
+    """One parameter set on one device (device=-1: host-only context)."""
+
+    def __init__(self, log_n, q_bits, p_bits, log_m=0, device=0, role=ROLE_KGC):
+        qb, _ = _ints(q_bits)
+        pb, _ = _ints(p_bits)
+        prm = LcParams(log_n, len(q_bits), len(p_bits), qb, pb, log_m)
+        h = VP()
+        rc = lib().lc_ctx_create(_c.byref(prm), device, role, _c.byref(h))
+        if rc != LC_OK:
+            raise LancelotError(rc, "lc_ctx_create failed")
+        self._h = h
+        self.device = device
+        li, nq, np_, dn = INT(), INT(), INT(), INT()
+        lib().lc_ctx_info(h, _c.byref(li), _c.byref(nq), _c.byref(np_), _c.byref(dn))
+        self.log_n, self.nq, self.np, self.dnum = li.value, nq.value, np_.value, dn.value
+        self.N = 1 << self.log_n
+        self.ne = self.nq + self.np
+        m = np.zeros(self.ne, dtype=np.uint64)
+        lib().lc_ctx_moduli(h, m.ctypes.data_as(PU64))
+        self.moduli = [int(x) for x in m]
+        self.q = self.moduli[: self.nq]
+        self.p = self.moduli[self.nq:]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != LC_OK:
+            msg = lib().lc_last_error(self._h)
+            raise LancelotError(rc, msg.decode() if msg else "")
+
+    # ---- shapes / allocation helpers (torch) ----
+    def empty(self, *shape, dtype=None):
+        import torch
+        return torch.empty(*shape, dtype=dtype or torch.int64, device=f"cuda:{self.device}")
+
+    def ct_words(self, ncomp=2):
+        return ncomp * self.nq * self.N
+
+    # ---- keys ----
+    def keygen(self, seed):
+        self._check(lib().lc_keygen(self._h, seed))
+
+    def keygen_rotation(self, seed, steps):
+        a, n = _ints(steps)
+        self._check(lib().lc_keygen_rotation(self._h, seed, a, n))
+
+    def keys_share(self, dst: "Context"):
+        self._check(lib().lc_keys_share(self._h, dst._h))
+
+    def secret(self):
+        out = np.zeros(self.N, dtype=np.int64)
+        self._check(lib().lc_secret_export(self._h, out.ctypes.data_as(PI64)))
+        return out
+
+    def pk(self):
+        out = np.zeros((2, self.nq, self.N), dtype=np.uint64)
+        self._check(lib().lc_pk_export(self._h, out.ctypes.data_as(PU64)))
+        return out
+
+    def ksk(self, which=0, step=0):
+        out = np.zeros((self.dnum, 2, self.ne, self.N), dtype=np.uint64)
+        self._check(lib().lc_ksk_export(self._h, which, step, out.ctypes.data_as(PU64)))
+        return out
+
+    def rotsum_steps(self, plan):
+        steps, j0 = [], 0
+        for kb in plan:
+            steps += [t << j0 for t in range(1, 1 << kb)]
+            j0 += kb
+        return steps
+
+    # ---- host encode / decode ----
+    def encode(self, z, scale):
+        z = np.asarray(z)
+        re_ = np.ascontiguousarray(z.real, dtype=np.float64)
+        im_ = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
+        out = np.zeros(self.N, dtype=np.int64)
+        self._check(lib().lc_encode(self._h, re_.ctypes.data_as(PD), im_.ctypes.data_as(PD) if im_ is not None
+                                    else None, len(re_), scale, out.ctypes.data_as(PI64)))
+        return out
+
+    def decode(self, residues, scale):
+        r = np.ascontiguousarray(residues, dtype=np.uint64)
+        re_ = np.zeros(self.N // 2)
+        im_ = np.zeros(self.N // 2)
+        self._check(lib().lc_decode(self._h, r.ctypes.data_as(PU64), scale, re_.ctypes.data_as(PD),
+                                    im_.ctypes.data_as(PD)))
+        return re_ + 1j * im_
+
+    def crt_to_double(self, residues):
+        """residues [nq][ncoeff] -> centred values as float64."""
+        r = np.ascontiguousarray(residues, dtype=np.uint64)
+        out = np.zeros(r.shape[1])
+        self._check(lib().lc_crt_to_double(self._h, r.ctypes.data_as(PU64), r.shape[1], r.shape[1],
+                                           out.ctypes.data_as(PD)))
+        return out
+
+    def gaussian_table(self):
+        out = np.zeros(38, dtype=np.uint64)
+        self._check(lib().lc_gaussian_table(self._h, out.ctypes.data_as(PU64)))
+        return out
+
+    # ---- device ops ----
+    def encrypt(self, m, seed, first_object=0, out=None, stream=None):
+        count = m.shape[0]
+        out = self.empty(count, 2, self.nq, self.N) if out is None else out
+        self._check(lib().lc_encrypt(self._h, _ptr(m), count, seed, first_object, _ptr(out), _stream(stream)))
+        return out
+
+    def decrypt(self, ct, ncomp=None, out=None, stream=None):
+        ncomp = ncomp or ct.shape[-3]
+        count = ct.numel() // (ncomp * self.nq * self.N)
+        out = self.empty(count, self.nq, self.N) if out is None else out
+        self._check(lib().lc_decrypt(self._h, _ptr(ct), ncomp, count, _ptr(out), _stream(stream)))
+        return out
+
+    def ct_sub(self, a, b, out=None, ncomp=2, stream=None):
+        out = self.empty(*a.shape) if out is None else out
+        count = a.numel() // self.ct_words(ncomp)
+        self._check(lib().lc_ct_sub(self._h, _ptr(a), _ptr(b), _ptr(out), count, ncomp, _stream(stream)))
+        return out
+
+    def ct_add(self, a, b, out=None, ncomp=2, stream=None):
+        out = self.empty(*a.shape) if out is None else out
+        count = a.numel() // self.ct_words(ncomp)
+        self._check(lib().lc_ct_add(self._h, _ptr(a), _ptr(b), _ptr(out), count, ncomp, _stream(stream)))
+        return out
+
+    def ct_mul(self, a, b, out=None, stream=None):
+        count = a.numel() // self.ct_words(2)
+        out = self.empty(count, 3, self.nq, self.N) if out is None else out
+        self._check(lib().lc_ct_mul(self._h, _ptr(a), _ptr(b), _ptr(out), count, _stream(stream)))
+        return out
+
+    def ct_square(self, a, out=None, stream=None):
+        count = a.numel() // self.ct_words(2)
+        out = self.empty(count, 3, self.nq, self.N) if out is None else out
+        self._check(lib().lc_ct_square(self._h, _ptr(a), _ptr(out), count, _stream(stream)))
+        return out
+
+    def relin(self, ct3, out=None, stream=None):
+        count = ct3.numel() // self.ct_words(3)
+        out = self.empty(count, 2, self.nq, self.N) if out is None else out
+        self._check(lib().lc_relin(self._h, _ptr(ct3), _ptr(out), count, _stream(stream)))
+        return out
+
+    def rotate_hoisted(self, ct, steps, out=None, stream=None):
+        count = ct.numel() // self.ct_words(2)
+        a, n = _ints(steps)
+        out = self.empty(count, n, 2, self.nq, self.N) if out is None else out
+        self._check(lib().lc_rotate_hoisted(self._h, _ptr(ct), count, a, n, _ptr(out), _stream(stream)))
+        return out
+
+    def rotate_sum(self, ct, plan=None, stream=None):
+        count = ct.numel() // self.ct_words(2)
+        if plan is None:
+            pa, n = None, 0
+        else:
+            pa, n = _ints(plan)
+        self._check(lib().lc_rotate_sum(self._h, _ptr(ct), count, pa, n, _stream(stream)))
+        return ct
+
+    def mul_plain(self, ct, pt, out=None, stream=None):
+        count = ct.numel() // self.ct_words(2)
+        out = self.empty(*ct.shape) if out is None else out
+        self._check(lib().lc_mul_plain(self._h, _ptr(ct), _ptr(pt), _ptr(out), count, _stream(stream)))
+        return out
+
+    def masked_sum(self, cts, masks, out=None, stream=None):
+        n, ln = cts.shape[0], cts.shape[1]
+        out = self.empty(ln, 2, self.nq, self.N) if out is None else out
+        self._check(lib().lc_masked_sum(self._h, _ptr(cts), n, ln, _ptr(masks), _ptr(out), _stream(stream)))
+        return out
+
+    def pair_triples(self, cts, out=None, stream=None):
+        n, ln = cts.shape[0], cts.shape[1]
+        P = n * (n - 1) // 2
+        out = self.empty(P, 3, self.nq, self.N) if out is None else out
+        self._check(lib().lc_pair_triples(self._h, _ptr(cts), n, ln, _ptr(out), _stream(stream)))
+        return out
+
+    def pairwise_sqdist(self, cts, plan=None, sumdis=False, out=None, sumdis_out=None, stream=None):
+        n, ln = cts.shape[0], cts.shape[1]
+        P = n * (n - 1) // 2
+        out = self.empty(P, 2, self.nq, self.N) if out is None else out
+        if sumdis and sumdis_out is None:
+            sumdis_out = self.empty(n, 2, self.nq, self.N)
+        if plan is None:
+            pa, nb = None, 0
+        else:
+            pa, nb = _ints(plan)
+        self._check(lib().lc_pairwise_sqdist(self._h, _ptr(cts), n, ln, pa, nb, _ptr(out),
+                                             _ptr(sumdis_out) if sumdis else None, _stream(stream)))
+        return (out, sumdis_out) if sumdis else out
+
+    def ntt_fwd(self, polys, nlimb, limb0=0, stream=None):
+        count = polys.numel() // (nlimb * self.N)
+        self._check(lib().lc_ntt_fwd(self._h, _ptr(polys), count, nlimb, limb0, _stream(stream)))
+        return polys
+
+    def ntt_inv(self, polys, nlimb, limb0=0, stream=None):
+        count = polys.numel() // (nlimb * self.N)
+        self._check(lib().lc_ntt_inv(self._h, _ptr(polys), count, nlimb, limb0, _stream(stream)))
+        return polys
+
+    def sync(self, stream=None):
+        self._check(lib().lc_sync(self._h, _stream(stream)))
+
+    def workspace_query(self, n, len_):
+        b = SZ()
+        self._check(lib().lc_workspace_query(self._h, n, len_, _c.byref(b)))
+        return b.value
+
+    def set_workspace_limit(self, nbytes):
+        self._check(lib().lc_set_workspace_limit(self._h, nbytes))
+
+    def device_bytes(self):
+        b = SZ()
+        self._check(lib().lc_ctx_device_bytes(self._h, _c.byref(b)))
+        return b.value

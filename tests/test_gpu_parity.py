@@ -1,0 +1,312 @@
+"""GPU parity: every device call of the C ABI against the CPU oracle on the
+same seeded inputs, bit for bit.
+
+Inputs are the oracle's (its encryptions, or synthetic residues from
+synth); the GPU never supplies an expected value.  Sizes span several NTT
+tiles and the ragged tails of the workloads.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2408_06197_amd import lancelot
+    lancelot.lib()
+    return lancelot
+
+
+def up(torch, arr):
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def down(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_pair(L, O, log_n, qb, pb, seed, steps=(), log_m=0):
+    """GPU context (KGC role) and oracle with the same parameters and keys."""
+    ctx = L.Context(log_n, qb, pb, log_m=log_m, device=0)
+    ctx.keygen(seed)
+    if steps:
+        ctx.keygen_rotation(seed, list(steps))
+    ora = O.Oracle(log_n, qb, pb, log_m=(log_m or None))
+    assert ora.primes == ctx.moduli
+    s = ora.secret(seed)
+    keys = {"s": s, "pk": ora.pk(seed, s), "rlk": ora.relin_key(seed, s)}
+    keys["rot"] = {k: ora.rot_key(seed, s, k) for k in steps}
+    return ctx, ora, keys
+
+
+TINY = (5, (30, 28, 28), (30,))
+TINY_A2 = (6, (45, 40, 40, 40, 40), (46, 46))
+CFG1 = (synth.CFG1.log_n, synth.CFG1.q_bits, synth.CFG1.p_bits)
+
+
+# ---- NTT ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("log_n", [3, 4, 5, 8, 11, 12, 13, 14, 15, 16])
+def test_ntt_bitexact(torch, L, oracle_mod, log_n):
+    O = oracle_mod
+    qb, pb = (50, 50, 40), (50, 45)
+    ctx = L.Context(log_n, qb, pb, device=0)
+    ora = O.Oracle(log_n, qb, pb)
+    count = 3 if log_n <= 14 else 2
+    x = synth.uniform_residues(1000 + log_n, ctx.moduli, (count, 1 << log_n))  # [count][ne][N]
+    g = up(torch, x)
+    ctx.ntt_fwd(g, nlimb=ctx.ne)
+    got = down(g)
+    for c in range(count):
+        want = np.vstack([ora.poly_ntt(x[c][l:l + 1], l) for l in range(ctx.ne)])
+        assert np.array_equal(got[c], want), (log_n, c)
+    ctx.ntt_inv(g, nlimb=ctx.ne)
+    assert np.array_equal(down(g), x)
+    # only the special-prime limbs (limb0 = n_q)
+    y = np.ascontiguousarray(x[:, ctx.nq:, :])
+    gy = up(torch, y)
+    ctx.ntt_fwd(gy, nlimb=ctx.np, limb0=ctx.nq)
+    want = np.vstack([ora.poly_ntt(y[0][k:k + 1], ctx.nq + k) for k in range(ctx.np)])
+    assert np.array_equal(down(gy)[0], want)
+
+
+def test_ntt_mixed_degree_chain(torch, L, oracle_mod):
+    """Primes = 1 mod 2^17 for every degree (the mixed-degree micro-workload's chain)."""
+    O = oracle_mod
+    for log_n in (12, 14, 16):
+        ctx = L.Context(log_n, (50, 50, 50), (50,), log_m=17, device=0)
+        ora = O.Oracle(log_n, (50, 50, 50), (50,), log_m=17)
+        x = synth.uniform_residues(7 + log_n, ctx.moduli[:3], (2, 1 << log_n))
+        g = up(torch, x)
+        ctx.ntt_fwd(g, nlimb=3)
+        for c in range(2):
+            assert np.array_equal(down(g)[c], ora.poly_ntt(x[c]))
+
+
+# ---- keys, encryption, decryption ---------------------------------------------
+
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
+def test_keys_bitexact(torch, L, oracle_mod, prm):
+    steps = [1, 2, 3, -1]
+    ctx, ora, keys = make_pair(L, oracle_mod, *prm, seed=2001, steps=steps)
+    assert np.array_equal(ctx.secret(), keys["s"])
+    assert np.array_equal(ctx.pk(), keys["pk"])
+    assert np.array_equal(ctx.ksk(0), keys["rlk"])
+    for k in steps:
+        assert np.array_equal(ctx.ksk(1, k), keys["rot"][k]), k
+
+
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
+def test_encrypt_decrypt_bitexact(torch, L, oracle_mod, prm):
+    O = oracle_mod
+    ctx, ora, keys = make_pair(L, O, *prm, seed=5)
+    rng = np.random.default_rng(3)
+    m = rng.integers(-(1 << 40), 1 << 40, size=(5, ctx.N), dtype=np.int64)
+    want = ora.encrypt(77, 1000, m, keys["pk"])
+    got = ctx.encrypt(torch.from_numpy(m).cuda(), seed=77, first_object=1000)
+    assert np.array_equal(down(got), want)
+    dec = down(ctx.decrypt(got))
+    for t in range(5):
+        assert np.array_equal(dec[t], ora.decrypt(want[t], keys["s"]))
+    # triples
+    t3 = ora.mul(want[0], want[1])
+    d3 = down(ctx.decrypt(up(torch, t3[None]), ncomp=3))[0]
+    assert np.array_equal(d3, ora.decrypt(t3, keys["s"]))
+
+
+# ---- element-wise ---------------------------------------------------------------
+
+@pytest.mark.parametrize("prm", [TINY, CFG1])
+def test_elementwise_bitexact(torch, L, oracle_mod, prm):
+    O = oracle_mod
+    ctx, ora, keys = make_pair(L, O, *prm, seed=9)
+    rng = np.random.default_rng(4)
+    m = rng.integers(-(1 << 30), 1 << 30, size=(6, ctx.N), dtype=np.int64)
+    cts = ora.encrypt(1, 0, m, keys["pk"])
+    a, b = up(torch, cts[:3]), up(torch, cts[3:])
+    sub, add = down(ctx.ct_sub(a, b)), down(ctx.ct_add(a, b))
+    mul, sq = down(ctx.ct_mul(a, b)), down(ctx.ct_square(a))
+    for t in range(3):
+        assert np.array_equal(sub[t], ora.sub(cts[t], cts[3 + t]))
+        assert np.array_equal(add[t], ora.add(cts[t], cts[3 + t]))
+        assert np.array_equal(mul[t], ora.mul(cts[t], cts[3 + t]))
+        assert np.array_equal(sq[t], ora.mul(cts[t], cts[t]))
+    # three-component add (lazy accumulation of triples)
+    acc = down(ctx.ct_add(ctx.ct_mul(a, b), ctx.ct_square(a), ncomp=3))
+    assert np.array_equal(acc[1], ora.add(ora.mul(cts[1], cts[4]), ora.mul(cts[1], cts[1])))
+    # plaintext multiply and masked aggregation
+    pts = synth.uniform_residues(5, ctx.q, (3, ctx.N))
+    mp = down(ctx.mul_plain(a, up(torch, pts)))
+    for t in range(3):
+        assert np.array_equal(mp[t], ora.mul_plain(cts[t], pts[t]))
+    client_cts = cts.reshape(3, 2, 2, ctx.nq, ctx.N)
+    masks = np.stack([ora.signed_to_ntt(np.array([w] + [0] * (ctx.N - 1))) for w in (0, 1, 5)])
+    ms = down(ctx.masked_sum(up(torch, client_cts), up(torch, masks)))
+    assert np.array_equal(ms, ora.masked_sum(client_cts, masks))
+
+
+# ---- key switching ---------------------------------------------------------------
+
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
+def test_relin_bitexact(torch, L, oracle_mod, prm):
+    O = oracle_mod
+    ctx, ora, keys = make_pair(L, O, *prm, seed=11)
+    rng = np.random.default_rng(6)
+    m = rng.integers(-(1 << 20), 1 << 20, size=(6, ctx.N), dtype=np.int64)
+    cts = ora.encrypt(2, 0, m, keys["pk"])
+    t3 = np.stack([ora.mul(cts[i], cts[i + 3]) for i in range(3)])
+    got = down(ctx.relin(up(torch, t3)))
+    for i in range(3):
+        assert np.array_equal(got[i], ora.relin(t3[i], keys["rlk"])), i
+
+
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
+def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm):
+    O = oracle_mod
+    steps = [1, 2, 5, -3]
+    ctx, ora, keys = make_pair(L, O, *prm, seed=13, steps=steps)
+    rng = np.random.default_rng(7)
+    m = rng.integers(-(1 << 20), 1 << 20, size=(2, ctx.N), dtype=np.int64)
+    cts = ora.encrypt(3, 0, m, keys["pk"])
+    got = down(ctx.rotate_hoisted(up(torch, cts), steps))
+    for c in range(2):
+        want = ora.rotate_hoisted(cts[c], steps, [keys["rot"][k] for k in steps])
+        assert np.array_equal(got[c], want), c
+
+
+@pytest.mark.parametrize("plan", ["ones", "twos", "three"])
+@pytest.mark.parametrize("prm", [TINY, TINY_A2])
+def test_rotate_sum_bitexact(torch, L, oracle_mod, prm, plan):
+    O = oracle_mod
+    levels = prm[0] - 1
+    plan = {"ones": [1] * levels, "twos": [2] * (levels // 2) + [1] * (levels % 2),
+            "three": [3] + [1] * (levels - 3)}[plan]
+    ora0 = O.Oracle(*prm)
+    steps = ora0.rotsum_steps(plan)
+    ctx, ora, keys = make_pair(L, O, *prm, seed=17, steps=steps)
+    rng = np.random.default_rng(8)
+    m = rng.integers(-(1 << 20), 1 << 20, size=(3, ctx.N), dtype=np.int64)
+    cts = ora.encrypt(4, 0, m, keys["pk"])
+    g = up(torch, cts)
+    ctx.rotate_sum(g, plan)
+    got = down(g)
+    for c in range(3):
+        want = ora.rotate_sum(cts[c], plan, [keys["rot"][k] for k in steps])
+        assert np.array_equal(got[c], want), c
+
+
+# ---- the pairwise pipeline -----------------------------------------------------------
+
+def encrypt_workload(O, ora, keys, w, seed):
+    upd = synth.client_updates(w)
+    scale = 2.0 ** w.scale_log2
+    m = np.stack([np.stack([O.encode(ch, w.log_n, scale) for ch in synth.pack(u, w.slots)]) for u in upd])
+    n, ln = m.shape[:2]
+    cts = ora.encrypt(seed, 0, m.reshape(n * ln, w.N), keys["pk"]).reshape(n, ln, 2, ora.nq, w.N)
+    return upd, m, cts
+
+
+def fp64_dists(upd):
+    n = upd.shape[0]
+    return np.array([np.sum((upd[i] - upd[j]) ** 2) for i in range(n) for j in range(i + 1, n)])
+
+
+TINY_W = synth.small_workload(log_n=5, q_bits=(45, 40, 40), p_bits=(45,), n_clients=4, dim=40, scale_log2=30)
+TINY_W5 = synth.small_workload(log_n=6, q_bits=(50, 45, 45, 45), p_bits=(50, 50), n_clients=5, dim=100,
+                               scale_log2=35, name="tiny5")
+TWO_W = synth.small_workload(log_n=6, q_bits=(50, 45, 45), p_bits=(50,), n_clients=2, dim=32, scale_log2=30,
+                             name="two-clients-one-ct")
+
+
+@pytest.mark.parametrize("w", [TINY_W, TINY_W5, TWO_W, synth.CFG1], ids=lambda w: w.name)
+def test_pairwise_pipeline_bitexact(torch, L, oracle_mod, w):
+    O = oracle_mod
+    ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    steps = ora0.rotsum_steps(w.rot_plan)
+    ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
+    upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
+    # GPU encryption of the same plaintexts gives the same ciphertexts
+    gcts = ctx.encrypt(torch.from_numpy(m.reshape(-1, w.N)).cuda(), seed=w.crypto_seed + 1)
+    assert np.array_equal(down(gcts).reshape(cts.shape), cts)
+    res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps], want_triples=True)
+    g = up(torch, cts)
+    trip = down(ctx.pair_triples(g))
+    assert np.array_equal(trip, res["triples"])
+    dist, sumdis = ctx.pairwise_sqdist(g, plan=list(w.rot_plan), sumdis=True)
+    assert np.array_equal(down(dist), res["dist"])
+    assert np.array_equal(down(sumdis), res["sumdis"])
+    # decrypted distances against FP64 (rtol 1e-3 at scale <= 2^35)
+    dec = down(ctx.decrypt(dist))
+    scale2 = 2.0 ** (2 * w.scale_log2)
+    got = ctx.crt_to_double(dec[:, :, 0].T.copy()) / scale2
+    assert np.allclose(got, fp64_dists(upd), rtol=1e-3)
+
+
+def test_cfg2_sampled_pairs(torch, L, oracle_mod):
+    """N=2^14, 8 limbs, 10 clients x 13 ciphertexts (ragged last one): all 45
+    distances decrypt to FP64 within 1e-4; three pairs are bit-exact against
+    the oracle, chosen to cover the first, a middle and the last pair."""
+    O = oracle_mod
+    w = synth.CFG2
+    ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    steps = ora0.rotsum_steps(w.rot_plan)
+    ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
+    upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
+    g = up(torch, cts)
+    dist = ctx.pairwise_sqdist(g, plan=list(w.rot_plan))
+    sample = [0, 22, 44]
+    res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps], want_sumdis=False,
+                       pairs=sample)
+    gd = down(dist)
+    for p in sample:
+        assert np.array_equal(gd[p], res["dist"][p]), p
+    dec = down(ctx.decrypt(dist))
+    got = ctx.crt_to_double(dec[:, :, 0].T.copy()) / 2.0 ** (2 * w.scale_log2)
+    assert np.allclose(got, fp64_dists(upd), rtol=1e-4)
+
+
+# ---- error paths ----------------------------------------------------------------------
+
+def test_error_paths(torch, L, oracle_mod):
+    ctx = L.Context(*TINY, device=0)
+    srv = L.Context(*TINY, device=0, role=L.ROLE_SERVER)
+    with pytest.raises(L.LancelotError) as e:
+        srv.keygen(1)
+    assert e.value.code == L.LC_EKEY
+    ctx.keygen(1)
+    ctx.keys_share(srv)
+    m = torch.zeros(1, ctx.N, dtype=torch.int64, device="cuda")
+    ct = srv.encrypt(m, seed=1)  # a server context can encrypt with the shared pk
+    with pytest.raises(L.LancelotError) as e:
+        srv.decrypt(ct)
+    assert e.value.code == L.LC_EKEY
+    with pytest.raises(L.LancelotError) as e:
+        srv.rotate_hoisted(ct, [1])
+    assert e.value.code == L.LC_EKEY
+    with pytest.raises(L.LancelotError) as e:
+        srv.rotate_sum(ct, [1, 1, 1, 1])
+    assert e.value.code == L.LC_EKEY
+    with pytest.raises(L.LancelotError) as e:
+        ctx.rotate_sum(ct, [2, 1])  # levels must sum to log_n - 1
+    assert e.value.code == L.LC_EINVAL
+    t3 = ctx.ct_square(ct)
+    with pytest.raises(L.LancelotError) as e:
+        ctx.relin(t3, out=t3.view(-1)[: 2 * ctx.nq * ctx.N].view(1, 2, ctx.nq, ctx.N))
+    assert e.value.code == L.LC_EINVAL
+    with pytest.raises(L.LancelotError) as e:
+        ctx.pair_triples(torch.zeros(1, 1, 2, ctx.nq, ctx.N, dtype=torch.int64, device="cuda"))
+    assert e.value.code == L.LC_EINVAL
+    # the shared keys relinearize identically in both contexts
+    a = ctx.relin(t3)
+    b = srv.relin(t3)
+    assert torch.equal(a, b)

@@ -1,0 +1,124 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol the
+header declares, and its host logic (prime rule, Gaussian table, encode,
+CRT, decode, argument checks) agrees with the oracle.  No GPU call is made:
+contexts here are host-only (device -1)."""
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2408_06197_amd import lancelot
+    return lancelot
+
+
+def test_exports_every_header_symbol(L):
+    lib = L.lib()
+    syms = L.header_symbols()
+    assert len(syms) >= 30
+    for s in syms:
+        assert hasattr(lib, s), s
+    # and the binding knows every one of them
+    assert set(syms) == set(L._SIGS), set(syms) ^ set(L._SIGS)
+
+
+CHAINS = [
+    (12, (40, 30, 30), (40,), 0),
+    (14, (50,) * 8, (50,) * 2, 0),
+    (16, (50,) * 24, (50,) * 4, 0),
+    (12, (50,) * 3, (50,), 17),
+    (14, (50,) * 6, (50,) * 2, 17),
+    (16, (50,) * 24, (50,) * 8, 17),
+    (5, (30, 28, 28), (30,), 0),
+]
+
+
+@pytest.mark.parametrize("log_n,qb,pb,log_m", CHAINS)
+def test_primes_match_oracle(L, oracle_mod, log_n, qb, pb, log_m):
+    ctx = L.Context(log_n, qb, pb, log_m=log_m, device=-1)
+    want = oracle_mod.find_primes(log_m or log_n + 1, list(qb) + list(pb))
+    assert ctx.moduli == want
+    assert ctx.dnum == -(-len(qb) // len(pb))
+
+
+def test_gaussian_table_matches_oracle(L, oracle_mod):
+    ctx = L.Context(5, (30,), (30,), device=-1)
+    assert np.array_equal(ctx.gaussian_table(), oracle_mod.cdt_table())
+
+
+@pytest.mark.parametrize("log_n", [4, 6, 12, 14, 16])
+def test_encode_within_one(L, oracle_mod, log_n):
+    """Two FP64 FFTs may differ in the last ulp; a coefficient may round the
+    other way, never by more than one."""
+    ctx = L.Context(log_n, (50, 50), (50,), device=-1)
+    rng = np.random.default_rng(log_n)
+    for scale_log2, z in [(40, rng.normal(0, 0.01, ctx.N // 2)), (30, rng.normal(0, 1, ctx.N // 3)),
+                          (40, rng.normal(size=ctx.N // 2) + 1j * rng.normal(size=ctx.N // 2))]:
+        a = ctx.encode(z, 2.0 ** scale_log2)
+        b = oracle_mod.encode(z, log_n, 2.0 ** scale_log2)
+        assert np.max(np.abs(a - b)) <= 1
+        assert np.mean(a != b) < 1e-3
+
+
+def test_encode_workload_chunk(L, oracle_mod):
+    w = synth.CFG2
+    ctx = L.Context(w.log_n, w.q_bits, w.p_bits, device=-1)
+    chunks = synth.pack(synth.client_updates(w, clients=[9])[0], w.slots)
+    for k in (0, w.n_ct - 1):  # a full chunk and the ragged last one
+        a = ctx.encode(chunks[k], 2.0 ** w.scale_log2)
+        b = oracle_mod.encode(chunks[k], w.log_n, 2.0 ** w.scale_log2)
+        assert np.max(np.abs(a - b)) <= 1
+
+
+@pytest.mark.parametrize("log_n,qb,pb", [(5, (30, 28, 28), (30,)), (12, (50,) * 16, (50,) * 4)])
+def test_crt_and_decode_match_oracle(L, oracle_mod, log_n, qb, pb):
+    ctx = L.Context(log_n, qb, pb, device=-1)
+    rng = np.random.default_rng(1)
+    Q = 1
+    for q in ctx.q:
+        Q *= q
+    # values spread over the whole centred range, plus small ones
+    vals = [int(rng.integers(0, 2**62)) * int(rng.integers(0, 2**62)) % Q - Q // 2 for _ in range(ctx.N - 4)]
+    vals += [0, 1, -1, Q // 2]
+    res = np.array([[v % q for v in vals] for q in ctx.q], dtype=np.uint64)
+    got = ctx.crt_to_double(res)
+    want = oracle_mod.crt_centered(res, ctx.q)
+    assert want[-1] == Q // 2 and want[-2] == -1
+    assert np.allclose(got, [float(v) for v in want], rtol=1e-15, atol=0)
+    # decode of a small plaintext
+    m = rng.integers(-2**40, 2**40, size=ctx.N)
+    res = np.array([[int(v) % q for v in m] for q in ctx.q], dtype=np.uint64)
+    z = ctx.decode(res, 2.0**30)
+    zo = oracle_mod.decode(m.astype(np.float64), log_n, 2.0**30)
+    assert np.allclose(z, zo, atol=1e-9 * np.max(np.abs(zo)))
+
+
+def test_crt_small_values_long_chain(L, oracle_mod):
+    """24 x 50-bit chain (Q ~ 2^1200): values of distance size come back exactly."""
+    ctx = L.Context(12, (50,) * 24, (50,) * 4, device=-1)
+    rng = np.random.default_rng(2)
+    vals = [int(rng.integers(-2**62, 2**62)) << int(rng.integers(0, 40)) for _ in range(200)]
+    res = np.array([[v % q for v in vals] for q in ctx.q], dtype=np.uint64)
+    got = ctx.crt_to_double(res)
+    assert [float(v) for v in oracle_mod.crt_centered(res, ctx.q)] == [float(v) for v in vals]
+    assert np.array_equal(got, np.array([float(v) for v in vals]))
+
+
+def test_argument_errors(L):
+    with pytest.raises(L.LancelotError) as e:
+        L.Context(17, (50,), (50,), device=-1)
+    assert e.value.code == L.LC_EUNSUP
+    with pytest.raises(L.LancelotError) as e:
+        L.Context(12, (55,), (50,), device=-1)
+    assert e.value.code == L.LC_EUNSUP
+    with pytest.raises(L.LancelotError) as e:
+        L.Context(12, (50,), (50,), log_m=5, device=-1)
+    assert e.value.code == L.LC_EINVAL
+    ctx = L.Context(5, (30, 28), (30,), device=-1)
+    # device calls on a host-only context are refused before touching a GPU
+    rc = L.lib().lc_keygen(ctx._h, 1)
+    assert rc == L.LC_EUNSUP
+    rc = L.lib().lc_ntt_fwd(ctx._h, None, 0, 1, 0, None)
+    assert rc == L.LC_EUNSUP
