@@ -1,0 +1,306 @@
+"""Benchmark: encrypted client-pair squared distances per second on one MI355X.
+
+One step = one pass of the server's hot path over one round of resident
+client ciphertexts: fused subtract/square/lazy-accumulate over all pairs and
+packed ciphertexts, one relinearization per pair, rotate-and-sum (block plan
+of hoisted rotations), SumDis, the plaintext-mask aggregation of every
+client ciphertext, and the KGC's decryption of the distance ciphertexts.
+Ingest (host FP64 encode + device encryption) happens before the timed
+region and is reported separately.
+
+Prints one JSON line (see --help for options).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
+    p.add_argument("--plan", default=None, help="rotate-sum block plan, e.g. 2,2,2,2,2,2,2,1")
+    p.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
+    p.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    p.add_argument("--oracle-cts", type=int, default=4, help="packed ciphertexts in the oracle's sample pair")
+    p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
+    p.add_argument("--stages", action="store_true", default=True, help="time each stage with events")
+    p.add_argument("--no-stages", dest="stages", action="store_false")
+    return p.parse_args()
+
+
+def fp64_pair_distances(upd):
+    g = upd @ upd.T
+    n = upd.shape[0]
+    d = np.diag(g)
+    return np.array([d[i] + d[j] - 2 * g[i, j] for i in range(n) for j in range(i + 1, n)])
+
+
+def event_time(torch, fn, reps=1):
+    """Average milliseconds of fn() on torch's current stream."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def ntt_roofline(torch, srv, batch):
+    """Forward NTT of `batch` ciphertext-sized blocks (batch x n_q limb-polys),
+    the shape the key-switch stages transform.  Returns per-launch figures:
+    two launches (passes) per transform, each with 8 N bytes of algorithmic
+    traffic per limb-polynomial (the transform's one read plus one write,
+    16 N bytes, split over its two launches)."""
+    x = torch.randint(0, 1 << 40, (batch, srv.nq, srv.N), dtype=torch.int64, device="cuda")
+    # residues must be below every q: 2^40 < 2^49 <= q_l
+    ms = event_time(torch, lambda: srv.ntt_fwd(x, nlimb=srv.nq), reps=5)
+    npoly = batch * srv.nq
+    launches = 2
+    per_launch_ms = ms / launches
+    bytes_per_launch = 8 * srv.N * npoly
+    del x
+    return {"launch_ms": per_launch_ms, "bytes_per_launch": bytes_per_launch, "limb_polys": npoly,
+            "transform_ms_per_limb_poly": ms / npoly}
+
+
+def cpu_baseline(w, plan, n_cts):
+    """The oracle on the host cores: one client pair with n_cts packed
+    ciphertexts (tensor phase), one relinearization and the full rotate-and-
+    sum; scaled to the full pair (LEN ciphertexts) and reported as distances/s."""
+    from oracle import oracle as O
+    import synth
+
+    ora = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    seed = w.crypto_seed
+    s = ora.secret(seed)
+    pk = ora.pk(seed, s)
+    rlk = ora.relin_key(seed, s)
+    rks = [ora.rot_key(seed, s, k) for k in ora.rotsum_steps(plan)]
+    upd = synth.client_updates(w, clients=[0, w.n_clients - 1])
+    scale = 2.0 ** w.scale_log2
+    k = min(n_cts, w.n_ct)
+    m = np.stack([np.stack([O.encode(c, w.log_n, scale) for c in synth.pack(u, w.slots)[:k]]) for u in upd])
+    cts = ora.encrypt(seed + 1, 0, m.reshape(2 * k, w.N), pk).reshape(2, k, 2, ora.nq, w.N)
+    t0 = time.perf_counter()
+    tri = ora.pair_triple(cts, 0, 1)
+    t1 = time.perf_counter()
+    d = ora.relin(tri, rlk)
+    t2 = time.perf_counter()
+    ora.rotate_sum(d, plan, rks)
+    t3 = time.perf_counter()
+    per_pair = (t1 - t0) * w.n_ct / k + (t3 - t1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / per_pair, "unit": "client-pair distances/s", "cores": cores, "kind": "oracle",
+            "sample": "one pair (clients 0, %d): tensor phase over %d of %d packed ciphertexts scaled x%.2f, plus "
+                      "1 relinearization and %d-block rotate-and-sum measured whole; oracle time %.1f s"
+                      % (w.n_clients - 1, k, w.n_ct, w.n_ct / k, len(plan), t3 - t0),
+            "seconds_per_pair": per_pair, "tensor_s": t1 - t0, "relin_s": t2 - t1, "rotsum_s": t3 - t2}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not supported (the packed-ciphertext axis would "
+              "shard across GPUs with one reduce-scatter of the triple accumulators).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2408_06197_amd import lancelot as L
+
+    w = synth.WORKLOADS[args.workload]
+    plan = [int(x) for x in args.plan.split(",")] if args.plan else list(w.rot_plan)
+    torch.cuda.set_device(0)
+    n, ln, N = w.n_clients, w.n_ct, w.N
+    P = w.n_pairs
+    scale = 2.0 ** w.scale_log2
+
+    t_setup = time.perf_counter()
+    kgc = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_KGC)
+    srv = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_SERVER)
+    kgc.keygen(w.crypto_seed)
+    kgc.keygen_rotation(w.crypto_seed, kgc.rotsum_steps(plan))
+    kgc.keys_share(srv)
+    t_keys = time.perf_counter() - t_setup
+    log(f"[bench] {w.name}: keys ready in {t_keys:.1f}s; ingesting {n} clients x {ln} ciphertexts")
+
+    # ---- ingest: host encode (threads), device encryption --------------------
+    nq = srv.nq
+    cts = torch.empty((n, ln, 2, nq, N), dtype=torch.int64, device="cuda")
+    upd_all = np.empty((n, w.dim), dtype=np.float64)
+    pool = cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+    t_enc_host = t_enc_dev = 0.0
+    for i in range(n):
+        upd = synth.client_updates(w, clients=[i])[0]
+        upd_all[i] = upd
+        chunks = synth.pack(upd, w.slots)
+        t0 = time.perf_counter()
+        m = np.stack(list(pool.map(lambda c: srv.encode(c, scale), chunks)))
+        t1 = time.perf_counter()
+        m_dev = torch.from_numpy(m).cuda()
+        srv.encrypt(m_dev, seed=w.crypto_seed + 1, first_object=i * ln, out=cts[i])
+        torch.cuda.synchronize()
+        t_enc_host += t1 - t0
+        t_enc_dev += time.perf_counter() - t1
+        del m_dev
+        if (i + 1) % 5 == 0 or i + 1 == n:
+            log(f"[bench] ingested {i + 1}/{n} clients")
+    ref = fp64_pair_distances(upd_all)
+    del upd_all
+    log(f"[bench] ingest: encode {t_enc_host:.1f}s (host), H2D+encrypt {t_enc_dev:.1f}s (device)")
+
+    # ---- buffers -----------------------------------------------------------------
+    dist = torch.empty((P, 2, nq, N), dtype=torch.int64, device="cuda")
+    sumdis = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
+    agg = torch.empty((ln, 2, nq, N), dtype=torch.int64, device="cuda")
+    dec = torch.empty((P, nq, N), dtype=torch.int64, device="cuda")
+    masks = torch.zeros((n, nq, N), dtype=torch.int64, device="cuda")
+    masks[0].fill_(1)  # one-hot plaintext mask on client 0 (constant 1 in the NTT domain)
+
+    def step():
+        srv.pairwise_sqdist(cts, plan=plan, sumdis=True, out=dist, sumdis_out=sumdis)
+        srv.masked_sum(cts, masks, out=agg)
+        kgc.decrypt(dist, out=dec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / max(1, args.steps)
+    value = P / (ms_per_step / 1e3)
+    log(f"[bench] {ms_per_step:.1f} ms/step -> {value:.1f} distances/s")
+
+    # ---- correctness of what was timed ------------------------------------------
+    d0 = dec[:, :, 0].cpu().numpy().view(np.uint64).T.copy()
+    got = kgc.crt_to_double(d0) / scale ** 2
+    rel = np.abs(got - ref) / np.abs(ref)
+    log(f"[bench] decrypted distances vs FP64: max rel err {rel.max():.2e} over {P} pairs")
+    check = {"max_rel_err_vs_fp64": float(rel.max()), "pairs": P, "ok": bool(rel.max() < 1e-4)}
+
+    extra = {}
+    if args.stages:
+        trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
+        t_a2 = event_time(torch, lambda: srv.pair_triples(cts, out=trip))
+        del trip
+        t_pipe = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=plan, sumdis=True, out=dist,
+                                                               sumdis_out=sumdis))
+        t_mask = event_time(torch, lambda: srv.masked_sum(cts, masks, out=agg))
+        t_dec = event_time(torch, lambda: kgc.decrypt(dist, out=dec))
+        extra["stage_ms"] = {"pair_triples": t_a2, "pairwise_total": t_pipe, "masked_sum": t_mask, "decrypt": t_dec}
+        log(f"[bench] stages (ms): {extra['stage_ms']}")
+
+    # ---- plain per-op form on a few pairs (lc_ct_sub / lc_ct_square / lc_ct_add per ciphertext) ------
+    if args.per_op_pairs:
+        pairs = [(0, 1), (n - 2, n - 1), (0, n - 1)][: args.per_op_pairs]
+        tmp = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+        sq = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+        acc = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+        out2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+
+        def per_op():
+            for (i, j) in pairs:
+                acc.zero_()
+                for k in range(ln):
+                    srv.ct_sub(cts[i, k], cts[j, k], out=tmp)
+                    srv.ct_square(tmp, out=sq)
+                    srv.ct_add(acc, sq, out=acc, ncomp=3)
+                srv.relin(acc, out=out2)
+                srv.rotate_sum(out2, plan)
+
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        per_op()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        extra["per_op_form"] = {"pairs_timed": len(pairs), "seconds_per_pair": tp / len(pairs),
+                                "distances_per_s": len(pairs) / tp}
+        log(f"[bench] per-op form: {tp / len(pairs) * 1e3:.1f} ms/pair -> {len(pairs) / tp:.2f} distances/s")
+
+    # ---- roofline of the dominant kernel ------------------------------------------
+    # Candidates: the fused pair-triple kernel (one launch per step, integer-ALU
+    # bound: 10 32x32->64 multiply-adds per update in the 25-bit split form) and
+    # the NTT passes of the key switches (HBM bound).  The one with the larger
+    # share of the step is reported.
+    roof = None
+    if args.stages:
+        nt = ntt_roofline(torch, srv, 64 if w.log_n >= 15 else 256)
+        ks_count = P * (1 + len(plan))
+        limb_ntts_per_ks = nq + srv.dnum * nq + 2 * srv.np + 2 * nq  # (L+1+K-alpha) = L+1 as alpha = K
+        ntt_ms_step = ks_count * limb_ntts_per_ks * nt["transform_ms_per_limb_poly"]
+        updates = P * ln * nq * N
+        a2 = {"bound": "alu", "achieved": 10 * updates / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e12,
+              "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "traffic": None, "kernel": "pair_triples_kernel",
+              "units_per_launch": "%d updates x 10 mad-ops" % updates,
+              "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
+        ntt = {"bound": "hbm", "achieved": nt["bytes_per_launch"] / (nt["launch_ms"] / 1e3) / 1e9,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "kernel": "ntt_fast_kernel",
+               "units_per_launch": "%d limb-polys x 8N bytes" % nt["limb_polys"], "launch_ms": nt["launch_ms"],
+               "est_ms_per_step": ntt_ms_step}
+        for r in (a2, ntt):
+            r["frac"] = r["achieved"] / r["peak"]
+        roof = ntt if ntt_ms_step > a2["est_ms_per_step"] else a2
+        extra["kernels"] = {"pair_triples": a2, "ntt": ntt}
+        log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} TOP/s, {a2['frac']:.1%} of VALU); "
+            f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step")
+
+    base = None
+    if args.cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample pair")
+        base = cpu_baseline(w, plan, args.oracle_cts)
+        log(f"[bench] oracle: {base['value']:.4f} distances/s ({base['sample']})")
+
+    out = {
+        "metric": "encrypted client-pair distances/s at N=2^16",
+        "value": value,
+        "unit": "client-pair distances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": N, "limbs": nq, "special_primes": srv.np, "dnum": srv.dnum,
+                   "clients": n, "dim": w.dim, "ciphertexts_per_client": ln, "pairs": P, "plan": plan,
+                   "scale_log2": w.scale_log2},
+        "check": check,
+        "ingest_s": {"encode_host": t_enc_host, "encrypt_device": t_enc_dev, "keygen": t_keys},
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

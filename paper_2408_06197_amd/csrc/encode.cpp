@@ -8,6 +8,8 @@
 // sum_k (m_k xi^k) w^tk, the conjugate DFT.
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "lc_internal.h"
@@ -16,10 +18,33 @@ namespace lc {
 
 typedef std::complex<double> cd;
 
-// In-place iterative radix-2 DFT: sign -1 computes sum_t a_t w^-tk.
+// Twiddle tables per transform size, built once: root[k] = exp(-2 pi i k / n)
+// for k < n/2, and the twist xi^-k = exp(-i pi k / N) for k < N.
+struct FftTables {
+    std::vector<cd> root, twist;
+};
+
+static const FftTables &tables(size_t n)
+{
+    static std::mutex mu;
+    static std::map<size_t, FftTables> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(n);
+    if (it != cache.end()) return it->second;
+    FftTables t;
+    t.root.resize(n / 2);
+    for (size_t k = 0; k < n / 2; k++) t.root[k] = std::polar(1.0, -2.0 * M_PI * (double)k / (double)n);
+    t.twist.resize(n);
+    for (size_t k = 0; k < n; k++) t.twist[k] = std::polar(1.0, -M_PI * (double)k / (double)n);
+    return cache.emplace(n, std::move(t)).first->second;
+}
+
+// In-place iterative radix-2 DFT: sign -1 computes sum_t a_t w^-tk, sign +1
+// the conjugate transform (w = exp(2 pi i / n)).
 static void dft(std::vector<cd> &a, int sign)
 {
     size_t n = a.size();
+    const FftTables &T = tables(n);
     for (size_t i = 1, j = 0; i < n; i++) {
         size_t bit = n >> 1;
         for (; j & bit; bit >>= 1) j ^= bit;
@@ -27,10 +52,11 @@ static void dft(std::vector<cd> &a, int sign)
         if (i < j) std::swap(a[i], a[j]);
     }
     for (size_t len = 2; len <= n; len <<= 1) {
-        double ang = sign * 2.0 * M_PI / (double)len;
+        size_t step = n / len;
         for (size_t s = 0; s < n; s += len)
             for (size_t k = 0; k < len / 2; k++) {
-                cd w(std::cos(ang * (double)k), std::sin(ang * (double)k));
+                cd w = T.root[k * step];
+                if (sign > 0) w = std::conj(w);
                 cd u = a[s + k], v = a[s + k + len / 2] * w;
                 a[s + k] = u + v;
                 a[s + k + len / 2] = u - v;
@@ -51,9 +77,9 @@ void encode_host(int log_n, const double *re, const double *im, size_t nslots, d
         e = (e * 5) % two_n;
     }
     dft(u, -1);
+    const FftTables &T = tables(N);
     for (size_t k = 0; k < N; k++) {
-        double ang = -M_PI * (double)k / (double)N;
-        double v = scale / (double)N * (u[k] * cd(std::cos(ang), std::sin(ang))).real();
+        double v = scale / (double)N * (u[k] * T.twist[k]).real();
         m[k] = (i64)(v >= 0 ? std::floor(v + 0.5) : -std::floor(-v + 0.5));
     }
 }
@@ -62,10 +88,8 @@ void decode_host(int log_n, const double *coeff, double scale, double *re, doubl
 {
     size_t N = (size_t)1 << log_n, two_n = 2 * N;
     std::vector<cd> a(N);
-    for (size_t k = 0; k < N; k++) {
-        double ang = M_PI * (double)k / (double)N;
-        a[k] = coeff[k] * cd(std::cos(ang), std::sin(ang));
-    }
+    const FftTables &T = tables(N);
+    for (size_t k = 0; k < N; k++) a[k] = coeff[k] * std::conj(T.twist[k]);
     dft(a, +1);
     size_t e = 1;
     for (size_t j = 0; j < N / 2; j++) {

@@ -112,7 +112,157 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(DevParams dp, Pol
     }
 }
 
-// Pass plan: one pass up to N = 4096, two passes above.
+// ---- register-radix pass kernel (N >= 2^10) ---------------------------------
+//
+// Same passes, faster execution: LOG_S in [5, 8] is a compile-time constant
+// and each lane owns 16 elements of one sub-transform.  The tile is staged in
+// LDS with coalesced global accesses; the pass then runs as two register
+// rounds separated by one LDS exchange:
+//   top round:    lane t holds a = (h << (LOG_S-4)) | t, h = 0..15 -- the four
+//                 stages acting on the top four bits of a;
+//   bottom round: lane t holds a = (t << 4) | h -- the remaining LOG_S - 4
+//                 stages (fewer than four leave independent groups).
+// Forward passes run top then bottom, inverse passes bottom then top.
+
+template <int LOG_S>
+__device__ __forceinline__ u32 lds_idx(u32 c, u32 a)
+{
+    constexpr u32 S = 1u << LOG_S;
+    return c * (S + S / 16) + a + (a >> 4);  // one pad word per 16 breaks bank strides
+}
+
+template <int LOG_S, bool INVERSE>
+__device__ __forceinline__ void ntt_round(u64 (&x)[16], bool top, u32 t, u64 hi, int s0, const u64 *tw,
+                                          const u64 *tws, u64 q)
+{
+    constexpr int LB = LOG_S - 4;
+    const u64 q2 = 2 * q;
+    // local stages of this round, in execution order
+    int first = top ? 0 : 4, last = top ? 3 : LOG_S - 1;
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+        int sl = INVERSE ? (last - it) : (first + it);
+        if (sl < first || sl > last) continue;
+        int bit = LOG_S - 1 - sl;                  // bit of a this stage pairs on
+        int hb = top ? (bit - LB) : bit;           // the same bit inside h
+        u64 base = (1ull << (s0 + sl)) + (hi << sl);
+#pragma unroll
+        for (int h = 0; h < 16; h++) {
+            if (h & (1 << hb)) continue;
+            u32 a1 = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
+            u64 ti = base + (a1 >> (LOG_S - sl));
+            u64 w = tw[ti], wsh = tws[ti];
+            u64 X = x[h], Y = x[h | (1 << hb)];
+            if (!INVERSE) {
+                X = csub(X, q2);
+                u64 T = mul_shoup_lazy(Y, w, wsh, q);
+                x[h] = X + T;
+                x[h | (1 << hb)] = X - T + q2;
+            } else {
+                x[h] = csub(X + Y, q2);
+                x[h | (1 << hb)] = mul_shoup_lazy(X - Y + q2, w, wsh, q);
+            }
+        }
+    }
+}
+
+template <int LOG_S, bool INVERSE, bool BLOCKS>
+__global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
+{
+    constexpr u32 S = 1u << LOG_S;
+    constexpr int LB = LOG_S - 4;
+    constexpr u32 TPC = S / 16;  // lanes per sub-transform
+    extern __shared__ u64 lds[];
+    u64 *poly;
+    int mi;
+    if (!poly_of_block(dp, pb, blockIdx.x, poly, mi)) return;
+    const u64 q = dp.mc[mi].m, q2 = 2 * q;
+    const u32 tile = blockIdx.y;
+    const u32 stride = dp.N >> (s0 + LOG_S);
+    const u32 nthreads = blockDim.x;
+    const u32 tid = threadIdx.x;
+    const u32 nel = S * (u32)cols;
+    const u64 *tw = (INVERSE ? dp.itw : dp.tw) + (u64)mi * dp.N;
+    const u64 *tws = (INVERSE ? dp.itw_sh : dp.tw_sh) + (u64)mi * dp.N;
+    // tile geometry
+    u64 hi_col = 0, lo0 = 0;
+    if (!BLOCKS) {
+        u32 lo_tiles = stride / (u32)cols;
+        hi_col = tile / lo_tiles;
+        lo0 = (u64)(tile % lo_tiles) * (u32)cols;
+    }
+    // coalesced load into LDS
+    for (u32 e = tid; e < nel; e += nthreads) {
+        u32 a, c;
+        u64 g;
+        if (BLOCKS) { c = e >> LOG_S; a = e & (S - 1); g = ((u64)tile * cols + c) * S + a; }
+        else { a = e / (u32)cols; c = e % (u32)cols; g = (hi_col * S + a) * stride + lo0 + c; }
+        lds[lds_idx<LOG_S>(c, a)] = poly[g];
+    }
+    __syncthreads();
+    const u32 c = tid / TPC, t = tid % TPC;
+    const u64 hi = BLOCKS ? ((u64)tile * cols + c) : hi_col;
+    u64 x[16];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        bool top = INVERSE ? (r == 1) : (r == 0);
+#pragma unroll
+        for (int h = 0; h < 16; h++) {
+            u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
+            x[h] = lds[lds_idx<LOG_S>(c, a)];
+        }
+        ntt_round<LOG_S, INVERSE>(x, top, t, hi, s0, tw, tws, q);
+#pragma unroll
+        for (int h = 0; h < 16; h++) {
+            u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
+            lds[lds_idx<LOG_S>(c, a)] = x[h];
+        }
+        __syncthreads();
+    }
+    const u64 ni = dp.ninv[mi], nish = dp.ninv_sh[mi];
+    for (u32 e = tid; e < nel; e += nthreads) {
+        u32 a, cc;
+        u64 g;
+        if (BLOCKS) { cc = e >> LOG_S; a = e & (S - 1); g = ((u64)tile * cols + cc) * S + a; }
+        else { a = e / (u32)cols; cc = e % (u32)cols; g = (hi_col * S + a) * stride + lo0 + cc; }
+        u64 v = lds[lds_idx<LOG_S>(cc, a)];
+        if (final_) {
+            if (INVERSE) v = mul_shoup(v, ni, nish, q);
+            else v = csub(csub(v, q2), q);
+        }
+        poly[g] = v;
+    }
+}
+
+struct FastPass {
+    int s0, log_s, blocks, cols;
+};
+
+// Two passes for 2^10 <= N <= 2^16: columns of the top half of the stages,
+// then contiguous blocks.  At most 4096 elements per workgroup.
+static int plan_fast(int log_n, FastPass *p)
+{
+    if (log_n < 10 || log_n > 16) return 0;
+    int k1 = log_n / 2, k2 = log_n - k1;  // k1 <= k2, both in [5, 8]
+    u32 stride1 = 1u << k2;
+    p[0] = {0, k1, 0, (int)std::min<u32>(4096u >> k1, stride1)};
+    p[1] = {k1, k2, 1, (int)std::min<u32>(4096u >> k2, 1u << k1)};
+    return 2;
+}
+
+template <bool INV, bool BLOCKS>
+static void launch_fast_one(int log_s, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &dp,
+                            const PolyBatch &b, int s0, int cols, int final_)
+{
+    switch (log_s) {
+    case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    }
+}
+
+// Pass plan of the generic kernel: one pass up to N = 4096, two passes above.
 static int plan_passes(int log_n, PassArgs *pass)
 {
     if (log_n <= 12) {
@@ -127,11 +277,32 @@ static int plan_passes(int log_n, PassArgs *pass)
 
 static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
 {
-    PassArgs pass[2];
-    int np = plan_passes(c->log_n, pass);
     u64 npoly = b.count * (u64)b.nlimb;
     if (npoly == 0) return LC_OK;
     if (npoly > 0x7fffffffull) return fail(c, LC_EINVAL, "too many polynomials in one NTT batch");
+    FastPass fp[2];
+    if (plan_fast(c->log_n, fp)) {
+        for (int k = 0; k < 2; k++) {
+            int i = inverse ? 1 - k : k;
+            const FastPass &P = fp[i];
+            int final_ = inverse ? (i == 0) : (i == 1);
+            u32 S = 1u << P.log_s;
+            u32 tiles = (u32)(c->N >> P.log_s) / (u32)P.cols;
+            dim3 grid((u32)npoly, tiles), block((u32)P.cols * (S / 16));
+            size_t lds = (size_t)P.cols * (S + S / 16) * sizeof(u64);
+            if (inverse) {
+                if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+                else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+            } else {
+                if (P.blocks) launch_fast_one<false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+                else launch_fast_one<false, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+            }
+            LC_HIP(c, hipGetLastError());
+        }
+        return LC_OK;
+    }
+    PassArgs pass[2];
+    int np = plan_passes(c->log_n, pass);
     for (int k = 0; k < np; k++) {
         int i = inverse ? np - 1 - k : k;
         PassArgs pa = pass[i];

@@ -137,15 +137,16 @@ int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, 
 
 // ---- fused subtract / square / lazy accumulate over all pairs --------------
 //
-// Workgroup = (coefficient tile of T lanes, limb l, chunk of pairs).  For
-// each packed ciphertext k the tiles of all n clients (both components) are
-// staged in LDS once and every pair of the chunk reads them from there; each
-// lane keeps PPT pairs' accumulators (three split sums per triple component)
-// in registers across all k, and reduces once at the end.
+// Workgroup = (coefficient tile of T lanes, limb l, chunk of pairs).  KB
+// packed ciphertexts at a time, the tiles of all n clients (both components)
+// are staged in LDS and every pair of the chunk reads them from there; each
+// lane keeps PPT pairs' accumulators (three split sums per triple component,
+// 18 VGPRs per pair) in registers across all k, and reduces once at the end.
 
 constexpr int PT_T = 16;        // coefficients per workgroup
 constexpr int PT_MAXN = 64;     // clients per call
 constexpr int PT_PPT = 3;       // pairs per lane
+constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
 
 __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
 {
@@ -158,64 +159,75 @@ __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
     j = row + 1 + (p - base);
 }
 
+template <int PPT, int KB>
 __global__ void __launch_bounds__(1024)
-pair_triples_kernel(DevParams dp, const u64 *cts, int n, int len, int P, u64 *d01, u64 d01_stride, u64 *d2,
-                    u64 d2_stride)
+pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int P, u64 *d01, u64 d01_stride,
+                    u64 *d2, u64 d2_stride)
 {
-    extern __shared__ u64 tile[];  // [n][2][T]
+    extern __shared__ u64 tile[];  // [KB][n][2][T]
     const int T = blockDim.x;      // coefficient lanes
     const int G = blockDim.y;      // pair groups
     const int lane = threadIdx.x, g = threadIdx.y;
     const int tid = g * T + lane;
     const int nthreads = T * G;
     const int l = blockIdx.y;
-    const u64 coef = (u64)blockIdx.x * T + lane;
     const u64 N = dp.N;
     const u64 S = (u64)dp.nq * N;
     const ModConst mc = dp.mc[l];
     const u64 q = mc.m;
+    const int per_k = n * 2 * T;
 
-    int pi[PT_PPT], pj[PT_PPT], pp[PT_PPT];
-    bool live[PT_PPT];
-    for (int r = 0; r < PT_PPT; r++) {
-        int p = blockIdx.z * (G * PT_PPT) + r * G + g;
+    int offa[PPT], offb[PPT], pp[PPT];
+    bool live[PPT];
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
+        int p = blockIdx.z * (G * PPT) + r * G + g;
         live[r] = p < P;
         pp[r] = p;
-        if (live[r]) pair_of_index(p, n, pi[r], pj[r]);
-        else pi[r] = pj[r] = 0;
+        int i = 0, j = 1;
+        if (live[r]) pair_of_index(p, n, i, j);
+        offa[r] = (i * 2) * T + lane;
+        offb[r] = (j * 2) * T + lane;
     }
-    Split3 acc[PT_PPT][3];
-    for (int r = 0; r < PT_PPT; r++)
+    Split3 acc[PPT][3];
+#pragma unroll
+    for (int r = 0; r < PPT; r++)
+#pragma unroll
         for (int c = 0; c < 3; c++) split_zero(acc[r][c]);
 
     const u64 client_stride = (u64)len * 2 * S;
     const u64 off = (u64)l * N + (u64)blockIdx.x * T;
-    for (int k = 0; k < len; k++) {
-        // stage tiles: element (i, comp, t)
-        for (int idx = tid; idx < n * 2 * T; idx += nthreads) {
-            int t = idx % T, ic = idx / T;  // ic = i * 2 + comp
+    for (int k0 = 0; k0 < len; k0 += KB) {
+        const int kb = min(KB, len - k0);
+        for (int idx = tid; idx < kb * per_k; idx += nthreads) {
+            int kk = idx / per_k, rem = idx - kk * per_k;
+            int t = rem % T, ic = rem / T;  // ic = i * 2 + comp
             int i = ic >> 1, comp = ic & 1;
-            tile[idx] = cts[(u64)i * client_stride + (u64)k * 2 * S + (u64)comp * S + off + t];
+            tile[idx] = cts[(u64)i * client_stride + (u64)(k0 + kk) * 2 * S + (u64)comp * S + off + t];
         }
         __syncthreads();
-        for (int r = 0; r < PT_PPT; r++) {
-            if (!live[r]) continue;
-            u64 a0 = tile[(pi[r] * 2) * T + lane], a1 = tile[(pi[r] * 2 + 1) * T + lane];
-            u64 b0 = tile[(pj[r] * 2) * T + lane], b1 = tile[(pj[r] * 2 + 1) * T + lane];
-            u64 x0 = sub_mod(a0, b0, q), x1 = sub_mod(a1, b1, q);
-            split_sq(acc[r][0], x0);
-            split_mac(acc[r][1], x0, x1);
-            split_sq(acc[r][2], x1);
+        for (int kk = 0; kk < kb; kk++) {
+            const u64 *tl = tile + kk * per_k;
+#pragma unroll
+            for (int r = 0; r < PPT; r++) {
+                if (!live[r]) continue;
+                u64 x0 = sub_mod(tl[offa[r]], tl[offb[r]], q);
+                u64 x1 = sub_mod(tl[offa[r] + T], tl[offb[r] + T], q);
+                split_sq(acc[r][0], x0);
+                split_mac(acc[r][1], x0, x1);
+                split_sq(acc[r][2], x1);
+            }
         }
         __syncthreads();
     }
-    for (int r = 0; r < PT_PPT; r++) {
+    const u64 o = (u64)l * N + (u64)blockIdx.x * T + lane;
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
         if (!live[r]) continue;
         u64 v0 = reduce_split_sq(acc[r][0], mc);
         u64 v1 = reduce_split(acc[r][1], mc);
         v1 = add_mod(v1, v1, q);
         u64 v2 = reduce_split_sq(acc[r][2], mc);
-        u64 o = (u64)l * N + coef;
         d01[(u64)pp[r] * d01_stride + o] = v0;
         d01[(u64)pp[r] * d01_stride + S + o] = v1;
         d2[(u64)pp[r] * d2_stride + o] = v2;
@@ -233,9 +245,9 @@ int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d0
     int G = std::min(groups_needed, 1024 / T);
     int chunks = (P + G * PT_PPT - 1) / (G * PT_PPT);
     dim3 grid((u32)(c->N / T), (u32)c->nq, (u32)chunks), block(T, G);
-    size_t lds = (size_t)n * 2 * T * sizeof(u64);
-    hipLaunchKernelGGL(pair_triples_kernel, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2,
-                       d2_stride);
+    size_t lds = (size_t)PT_KB * n * 2 * T * sizeof(u64);
+    hipLaunchKernelGGL((pair_triples_kernel<PT_PPT, PT_KB>), grid, block, lds, s, c->dp, cts, n, len, P, d01,
+                       d01_stride, d2, d2_stride);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }
