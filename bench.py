@@ -38,11 +38,16 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
-    p.add_argument("--plan", default=None, help="rotate-sum block plan, e.g. 2,2,2,2,2,2,2,1")
+    p.add_argument("--plan", default=None, help="rotate-sum block plan, e.g. 2,2,2,2,2,2,2,1 (default: autotuned)")
+    p.add_argument("--no-tune", dest="tune", action="store_false", default=True,
+                   help="skip the launch-shape / plan autotuner")
     p.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     p.add_argument("--oracle-cts", type=int, default=4, help="packed ciphertexts in the oracle's sample pair")
     p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
+    p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
+                   help="also run the serving form: ROUNDS Poisson-arriving aggregation rounds")
+    p.add_argument("--serve-slots", type=int, default=4)
     p.add_argument("--stages", action="store_true", default=True, help="time each stage with events")
     p.add_argument("--no-stages", dest="stages", action="store_false")
     return p.parse_args()
@@ -120,6 +125,78 @@ def cpu_baseline(w, plan, n_cts):
             "seconds_per_pair": per_pair, "tensor_s": t1 - t0, "relin_s": t2 - t1, "rotsum_s": t3 - t2}
 
 
+def serve_bench(args, torch, L, srv16, kgc16, plan16):
+    """Serving form: Poisson stream of aggregation rounds over the N=2^14
+    (8 limbs) and N=2^16 (24 limbs) parameter sets, 5..40 clients, 1e5..1.12e7
+    dims, continuous admission by HBM footprint; returns rounds/s, p50, p99."""
+    from paper_2408_06197_amd import serve
+    import synth
+
+    w14, w16 = synth.CFG2, synth.CFG3
+    chains = {"n16384_l8": serve.ChainInfo("n16384_l8", 14, 8, 2, 40),
+              "n65536_l24": serve.ChainInfo("n65536_l24", 16, 24, 4, 40)}
+    kgc14 = L.Context(w14.log_n, w14.q_bits, w14.p_bits, device=0, role=L.ROLE_KGC)
+    srv14 = L.Context(w14.log_n, w14.q_bits, w14.p_bits, device=0, role=L.ROLE_SERVER)
+    plan14 = [3] * 4 + [1]
+    kgc14.keygen(w14.crypto_seed)
+    kgc14.keygen_rotation(w14.crypto_seed, kgc14.rotsum_steps(plan14))
+    kgc14.keys_share(srv14)
+    contexts = {"n16384_l8": (kgc14, srv14), "n65536_l24": (kgc16, srv16)}
+    plans = {"n16384_l8": plan14, "n65536_l24": plan16}
+    k_chunk = 32
+    for c in (srv14, srv16):
+        c.set_tuning("ks_chunk", 32)
+    t0 = time.perf_counter()
+    pools = {}
+    for name, ch in chains.items():
+        ctx = contexts[name][1]
+        tails = sorted({d - (ch.n_ct(d) - 1) * ch.slots for d in (100_000, 1_000_000, 11_200_000)})
+        pools[name] = serve.PlaintextPool(torch, ctx, size=64, std=0.01, seed=3001, scale=2.0 ** ch.scale_log2,
+                                          tails=[t for t in tails if t < ch.slots])
+    log(f"[bench] serving: pools encoded in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    # leave room for the library's per-stream scratch (key switching, rotation
+    # ping-pong, encryption staging: about 10 GB per stream) and torch's cache
+    budget = int(free * 0.5)
+    names = list(chains)
+
+    def run(specs):
+        ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=k_chunk, streams=args.serve_slots)
+        return serve.Scheduler(chains, budget, slots=args.serve_slots, k_chunk=k_chunk).run(specs, ex)
+
+    # closed-loop calibration: a burst of rounds arriving together
+    calib = serve.make_stream(8, rate=0.0, chains=names, seed=2999)
+    t0 = time.perf_counter()
+    rec = run(calib)
+    torch.cuda.synchronize()
+    capacity = len(calib) / (time.perf_counter() - t0)
+    rate = 0.7 * capacity
+    del rec
+    torch.cuda.empty_cache()
+    log(f"[bench] serving: closed-loop capacity {capacity:.2f} rounds/s; Poisson rate {rate:.2f}/s")
+    specs = serve.make_stream(args.serve, rate=rate, chains=names, seed=3000)
+    t0 = time.perf_counter()
+    rec = run(specs)
+    wall = time.perf_counter() - t0
+    st = serve.latency_stats(rec)
+    # spot-check decryption of a few rounds against FP64
+    errs = []
+    for rid in list(rec)[:6]:
+        sp = specs[rid]
+        ref = serve.reference_distances(sp, pools[sp.chain], chains[sp.chain].n_ct(sp.dim))
+        got = rec[rid]["result"]["distances"]
+        errs.append(float(np.max(np.abs(got - ref) / np.abs(ref))))
+    st.update({"wall_s": wall, "slots": args.serve_slots, "k_chunk": k_chunk, "budget_bytes": budget,
+               "rate_per_s": rate, "calibrated_capacity_per_s": capacity, "checked_rounds": len(errs),
+               "max_rel_err_vs_fp64": max(errs) if errs else None,
+               "by_chain": {c: serve.latency_stats({k: v for k, v in rec.items() if v["chain"] == c})
+                            for c in names if any(v["chain"] == c for v in rec.values())}})
+    log(f"[bench] serving: {st['rounds']} rounds in {wall:.1f}s, {st['rounds_per_s']:.2f} rounds/s, "
+        f"p50 {st['p50_s']:.3f}s p99 {st['p99_s']:.3f}s, max rel err {st['max_rel_err_vs_fp64']}")
+    return st
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -132,7 +209,12 @@ def main():
     from paper_2408_06197_amd import lancelot as L
 
     w = synth.WORKLOADS[args.workload]
-    plan = [int(x) for x in args.plan.split(",")] if args.plan else list(w.rot_plan)
+    levels = w.log_n - 1
+    if args.plan:
+        plans = [[int(x) for x in args.plan.split(",")]]
+    else:  # dynamic hoisting: blocks of 1, 2 or 3 levels, chosen by measurement
+        plans = [[1] * levels, [2] * (levels // 2) + [1] * (levels % 2), [3] * (levels // 3) + [1] * (levels % 3)]
+    plan = plans[0]
     torch.cuda.set_device(0)
     n, ln, N = w.n_clients, w.n_ct, w.N
     P = w.n_pairs
@@ -142,7 +224,7 @@ def main():
     kgc = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_KGC)
     srv = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_SERVER)
     kgc.keygen(w.crypto_seed)
-    kgc.keygen_rotation(w.crypto_seed, kgc.rotsum_steps(plan))
+    kgc.keygen_rotation(w.crypto_seed, sorted({s for pl in plans for s in kgc.rotsum_steps(pl)}))
     kgc.keys_share(srv)
     t_keys = time.perf_counter() - t_setup
     log(f"[bench] {w.name}: keys ready in {t_keys:.1f}s; ingesting {n} clients x {ln} ciphertexts")
@@ -179,6 +261,34 @@ def main():
     dec = torch.empty((P, nq, N), dtype=torch.int64, device="cuda")
     masks = torch.zeros((n, nq, N), dtype=torch.int64, device="cuda")
     masks[0].fill_(1)  # one-hot plaintext mask on client 0 (constant 1 in the NTT domain)
+
+    # ---- autotuner: pair-kernel launch shape, then the hoisting plan -------------
+    tuned = {}
+    if args.tune:
+        trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
+        best = None
+        for lanes in (16, 32, 64):
+            for ppt in (3, 6):
+                srv.set_tuning("pair_lanes", lanes)
+                srv.set_tuning("pair_ppt", ppt)
+                ms = event_time(torch, lambda: srv.pair_triples(cts, out=trip))
+                tuned.setdefault("pair_kernel_ms", {})["%dx%d" % (lanes, ppt)] = ms
+                if best is None or ms < best[0]:
+                    best = (ms, lanes, ppt)
+        del trip
+        srv.set_tuning("pair_lanes", best[1])
+        srv.set_tuning("pair_ppt", best[2])
+        tuned["pair_lanes"], tuned["pair_ppt"] = best[1], best[2]
+        if len(plans) > 1:
+            bestp = None
+            for pl in plans:
+                ms = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=pl, out=dist))
+                tuned.setdefault("plan_ms", {})[",".join(map(str, pl))] = ms
+                if bestp is None or ms < bestp[0]:
+                    bestp = (ms, pl)
+            plan = bestp[1]
+        tuned["plan"] = plan
+        log(f"[bench] autotuned: {tuned}")
 
     def step():
         srv.pairwise_sqdist(cts, plan=plan, sumdis=True, out=dist, sumdis_out=sumdis)
@@ -271,6 +381,14 @@ def main():
         log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} TOP/s, {a2['frac']:.1%} of VALU); "
             f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step")
 
+    if args.serve:
+        del cts
+        torch.cuda.empty_cache()
+        if w.log_n != 16:
+            log("[bench] --serve needs the N=2^16 workload's contexts; skipped")
+        else:
+            extra["serving"] = serve_bench(args, torch, L, srv, kgc, plan)
+
     base = None
     if args.cpu_baseline:
         log("[bench] timing the CPU oracle on a sample pair")
@@ -298,6 +416,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": base,
     }
+    out["autotune"] = tuned
     out.update(extra)
     print(json.dumps(out), flush=True)
 

@@ -22,7 +22,8 @@
  *   lc_ctx_destroy.
  * Streams.  `stream` is a hipStream_t (NULL: the default stream).  Device
  *   calls are asynchronous on it; lc_sync waits and reports asynchronous
- *   errors.  Calls on one context must come from one host thread at a time.
+ *   errors.  Calls on one context must come from one host thread at a time;
+ *   growing a stream's workspace waits for that stream.
  * Errors.  Every call returns LC_OK (0) or a negative code; lc_last_error
  *   gives text.  Nothing is written to outputs when a call returns an error
  *   before launching work.
@@ -178,10 +179,20 @@ int lc_masked_sum(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, c
 /* ---- the pairwise-distance pipeline (Algorithm 1, Server Executes) ------- */
 
 /* Lazy triples only: for pairs i < j in row-major order, sum over k < len of
- * (ct_i[k] - ct_j[k])^2 as triples.  triples [P][3][n_q][N], P = n(n-1)/2.
- * len <= 4096. */
+ * (ct_i[k] - ct_j[k])^2 as triples.  triples [P][3][n_q][N], P = n(n-1)/2,
+ * 2 <= n <= 64. */
 int lc_pair_triples(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, uint64_t *triples_dev,
                     void *stream);
+/* Same, adding into triples (which must hold canonical residues): lets a
+ * round stream its packed ciphertexts in chunks of k (Methods, Lazy
+ * Relinearization: triples of all k are summed before one relinearization). */
+int lc_pair_triples_acc(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, uint64_t *triples_dev,
+                        void *stream);
+/* The rest of the pipeline on accumulated triples [P][3][n_q][N]: one
+ * relinearization per pair, rotate-and-sum with `plan`, SumDis (may be NULL).
+ * dist [P][2][n_q][N] must not overlap the triples. */
+int lc_pairwise_finish(lc_ctx *ctx, const uint64_t *triples_dev, int n, const int *plan, int nblocks,
+                       uint64_t *dist_dev, uint64_t *sumdis_dev, void *stream);
 /* Full batched pipeline: lazy triples, one relinearization per pair,
  * rotate-and-sum with `plan`; dist [P][2][n_q][N].  sumdis (may be NULL)
  * [n][2][n_q][N] gets sum over j != i of Dis[i][j]. */
@@ -203,6 +214,12 @@ int lc_workspace_query(const lc_ctx *ctx, int n, int len, size_t *bytes);
 /* Caps the workspace the library may hold (0 = no cap); calls that would
  * need more run in smaller batches, or fail with LC_ENOMEM. */
 int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
+
+/* Launch-shape tuning, results unchanged (every shape computes the same
+ * residues): "pair_lanes" (8/16/32/64 coefficients per workgroup of the pair
+ * kernel), "pair_ppt" (1/3/6 pairs per lane), "ks_chunk" (1..256
+ * ciphertexts per key-switch batch).  LC_EINVAL for unknown names/values. */
+int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 
 #ifdef __cplusplus
 }

@@ -27,14 +27,15 @@ int hip_fail(Ctx *c, hipError_t e, const char *what)
     return fail(c, LC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-u64 *ws_get(Ctx *c, int slot, size_t bytes)
+u64 *ws_get(Ctx *c, int slot, size_t bytes, hipStream_t s)
 {
-    if (c->slot_bytes[slot] >= bytes && c->slot[slot]) return (u64 *)c->slot[slot];
-    if (c->slot[slot]) {
-        hipDeviceSynchronize();
-        hipFree(c->slot[slot]);
-        c->slot[slot] = nullptr;
-        c->slot_bytes[slot] = 0;
+    Ctx::Workspace &w = c->ws[s];
+    if (w.bytes[slot] >= bytes && w.slot[slot]) return (u64 *)w.slot[slot];
+    if (w.slot[slot]) {
+        hipStreamSynchronize(s);
+        hipFree(w.slot[slot]);
+        w.slot[slot] = nullptr;
+        w.bytes[slot] = 0;
     }
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -42,8 +43,8 @@ u64 *ws_get(Ctx *c, int slot, size_t bytes)
         c->err = "workspace allocation of " + std::to_string(bytes) + " bytes failed";
         return nullptr;
     }
-    c->slot[slot] = p;
-    c->slot_bytes[slot] = bytes;
+    w.slot[slot] = p;
+    w.bytes[slot] = bytes;
     return (u64 *)p;
 }
 
@@ -72,7 +73,7 @@ static int gen_ksk(Ctx *c, u64 seed, u64 key_id, const u64 *t_ntt, u64 *ksk)
 {
     const int ne = c->ne, nq = c->nq, alpha = c->alpha;
     const u64 N = c->N, NE = (u64)ne * N;
-    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8);
+    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8, 0);
     if (!tmp) return LC_ENOMEM;
     u64 *e_ntt = tmp;
     i64 *e_coef = (i64 *)(tmp + NE);
@@ -94,6 +95,12 @@ static int gen_ksk(Ctx *c, u64 seed, u64 key_id, const u64 *t_ntt, u64 *ksk)
     }
     LC_HIP(c, hipDeviceSynchronize());
     return LC_OK;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
 }
 
 static Ctx *C(lc_ctx *x) { return x ? &x->c : nullptr; }
@@ -152,8 +159,9 @@ int lc_ctx_destroy(lc_ctx *x)
         hipSetDevice(c->device);
         hipDeviceSynchronize();
         for (void *p : c->allocs) hipFree(p);
-        for (int i = 0; i < 8; i++)
-            if (c->slot[i]) hipFree(c->slot[i]);
+        for (auto &kv : c->ws)
+            for (int i = 0; i < 8; i++)
+                if (kv.second.slot[i]) hipFree(kv.second.slot[i]);
     }
     delete x;
     return LC_OK;
@@ -190,7 +198,8 @@ int lc_ctx_device_bytes(const lc_ctx *x, size_t *bytes)
 {
     if (!x || !bytes) return LC_EINVAL;
     size_t b = x->c.table_bytes + x->c.key_bytes;
-    for (int i = 0; i < 8; i++) b += x->c.slot_bytes[i];
+    for (auto &kv : x->c.ws)
+        for (int i = 0; i < 8; i++) b += kv.second.bytes[i];
     *bytes = b;
     return LC_OK;
 }
@@ -227,7 +236,7 @@ int lc_keygen(lc_ctx *x, uint64_t seed)
     if ((rc = upload_shoup(c, c->sk_ntt, c->sk_ntt_sh, ne, 1))) return rc;
     if ((rc = upload_shoup(c, c->sk2_ntt, c->sk2_ntt_sh, nq, 1))) return rc;
     // public key: a uniform (NTT domain), e Gaussian
-    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8);
+    u64 *tmp = ws_get(c, WS_KEYGEN, (NE + N + ne) * 8, 0);
     if (!tmp) return LC_ENOMEM;
     u64 *e_ntt = tmp;
     i64 *e_coef = (i64 *)(tmp + NE);
@@ -239,7 +248,7 @@ int lc_keygen(lc_ctx *x, uint64_t seed)
     LC_HIP(c, hipDeviceSynchronize());
     if ((rc = upload_shoup(c, c->pk, c->pk_sh, nq, 2))) return rc;
     // relinearization key: target s^2 over all ne limbs
-    u64 *t = ws_get(c, WS_TMP, NE * 8);
+    u64 *t = ws_get(c, WS_TMP, NE * 8, 0);
     if (!t) return LC_ENOMEM;
     if ((rc = launch_pointwise_sq(c, c->sk_ntt, t, ne, 0))) return rc;
     if ((rc = gen_ksk(c, seed, 0, t, c->rlk))) return rc;
@@ -255,7 +264,7 @@ int lc_keygen_rotation(lc_ctx *x, uint64_t seed, const int *steps, int nsteps)
     if (!c->sk_ntt) return fail(c, LC_EKEY, "call lc_keygen first");
     if (nsteps < 0 || (nsteps && !steps)) return fail(c, LC_EINVAL, "bad steps");
     const u64 NE = (u64)c->ne * c->N;
-    u64 *t = ws_get(c, WS_TMP, NE * 8);
+    u64 *t = ws_get(c, WS_TMP, NE * 8, 0);
     if (!t) return LC_ENOMEM;
     for (int i = 0; i < nsteps; i++) {
         u64 g = galois_of_step(c->log_n, steps[i]);
@@ -382,7 +391,7 @@ int lc_encrypt(lc_ctx *x, const int64_t *m, size_t count, uint64_t seed, uint64_
     hipStream_t s = (hipStream_t)stream;
     const u64 S = (u64)c->nq * c->N;
     u64 chunk = std::min<u64>(count, std::max<u64>(1, (1ull << 31) / (3 * S * 8)));
-    u64 *tmp = ws_get(c, WS_ENC, chunk * 3 * S * 8);
+    u64 *tmp = ws_get(c, WS_ENC, chunk * 3 * S * 8, s);
     if (!tmp) return LC_ENOMEM;
     for (u64 t0 = 0; t0 < count; t0 += chunk) {
         u64 B = std::min<u64>(chunk, count - t0);
@@ -439,11 +448,6 @@ int lc_ct_square(lc_ctx *x, const uint64_t *a, uint64_t *out3, size_t count, voi
     return launch_tensor(c, a, nullptr, out3, count, (hipStream_t)stream);
 }
 
-static bool overlap(const void *a, size_t na, const void *b, size_t nb)
-{
-    const char *x = (const char *)a, *y = (const char *)b;
-    return x < y + nb && y < x + na;
-}
 
 int lc_relin(lc_ctx *x, const uint64_t *ct3, uint64_t *ct2, size_t count, void *stream)
 {
@@ -525,8 +529,8 @@ int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nb
         blocks.push_back(G);
         j0 += k;
     }
-    u64 chunk = std::min<u64>(count, 64);
-    u64 *other = ws_get(c, WS_ROT, chunk * 2 * S * 8);
+    u64 chunk = std::min<u64>(count, (u64)c->tune.ks_chunk);
+    u64 *other = ws_get(c, WS_ROT, chunk * 2 * S * 8, s);
     if (!other) return LC_ENOMEM;
     for (u64 b0 = 0; b0 < count; b0 += chunk) {
         u64 B = std::min<u64>(chunk, count - b0);
@@ -570,7 +574,52 @@ int lc_pair_triples(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t *tr
     CHECK_CTX(x);
     if (!cts || !triples) return fail(c, LC_EINVAL, "null buffer");
     const u64 S = (u64)c->nq * c->N;
-    return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, (hipStream_t)stream);
+    return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, 0, (hipStream_t)stream);
+}
+
+int lc_pair_triples_acc(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t *triples, void *stream)
+{
+    CHECK_CTX(x);
+    if (!cts || !triples) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, 1, (hipStream_t)stream);
+}
+
+// relinearize the triples whose (d0, d1) sit at `d01` (stride 2S, becoming
+// the distances in place) and whose d2 sit at `d2` (stride d2_stride), then
+// rotate-and-sum and SumDis.
+static int pairwise_finish(lc_ctx *x, Ctx *c, const u64 *d01_base, u64 d01_stride, const u64 *d2, u64 d2_stride,
+                           int n, const int *plan, int nblocks, uint64_t *dist, uint64_t *sumdis, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
+    const u64 P = (u64)n * (n - 1) / 2;
+    KsGroup g{};
+    g.keys[0] = c->rlk;
+    g.n = 1;
+    g.base = d01_base;
+    g.base_stride = d01_stride;
+    g.out = dist;
+    g.out_stride = 2 * S;
+    int rc;
+    if ((rc = keyswitch_hoisted(c, d2, d2_stride, P, &g, 1, s))) return rc;
+    if ((rc = lc_rotate_sum(x, dist, P, plan, nblocks, stream))) return rc;
+    if (sumdis) return launch_sumdis(c, dist, n, sumdis, s);
+    return LC_OK;
+}
+
+int lc_pairwise_finish(lc_ctx *x, const uint64_t *triples, int n, const int *plan, int nblocks, uint64_t *dist,
+                       uint64_t *sumdis, void *stream)
+{
+    CHECK_CTX(x);
+    if (!triples || !dist) return fail(c, LC_EINVAL, "null buffer");
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    if (n < 2 || n > 64) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
+    const u64 S = (u64)c->nq * c->N;
+    const u64 P = (u64)n * (n - 1) / 2;
+    if (overlap(triples, P * 3 * S * 8, dist, P * 2 * S * 8))
+        return fail(c, LC_EINVAL, "dist must not overlap the triples");
+    return pairwise_finish(x, c, triples, 3 * S, triples + 2 * S, 3 * S, n, plan, nblocks, dist, sumdis, stream);
 }
 
 int lc_pairwise_sqdist(lc_ctx *x, const uint64_t *cts, int n, int len, const int *plan, int nblocks, uint64_t *dist,
@@ -583,21 +632,11 @@ int lc_pairwise_sqdist(lc_ctx *x, const uint64_t *cts, int n, int len, const int
     hipStream_t s = (hipStream_t)stream;
     const u64 S = (u64)c->nq * c->N;
     const u64 P = (u64)n * (n - 1) / 2;
-    u64 *d2 = ws_get(c, WS_PIPE, P * S * 8);
+    u64 *d2 = ws_get(c, WS_PIPE, P * S * 8, s);
     if (!d2) return LC_ENOMEM;
     int rc;
-    if ((rc = launch_pair_triples(c, cts, n, len, dist, 2 * S, d2, S, s))) return rc;
-    KsGroup g{};
-    g.keys[0] = c->rlk;
-    g.n = 1;
-    g.base = dist;
-    g.base_stride = 2 * S;
-    g.out = dist;
-    g.out_stride = 2 * S;
-    if ((rc = keyswitch_hoisted(c, d2, S, P, &g, 1, s))) return rc;
-    if ((rc = lc_rotate_sum(x, dist, P, plan, nblocks, stream))) return rc;
-    if (sumdis) return launch_sumdis(c, dist, n, sumdis, s);
-    return LC_OK;
+    if ((rc = launch_pair_triples(c, cts, n, len, dist, 2 * S, d2, S, 0, s))) return rc;
+    return pairwise_finish(x, c, dist, 2 * S, d2, S, n, plan, nblocks, dist, sumdis, stream);
 }
 
 int lc_ntt_fwd(lc_ctx *x, uint64_t *polys, size_t count, int nlimb, int limb0, void *stream)
@@ -629,8 +668,28 @@ int lc_workspace_query(const lc_ctx *x, int n, int len, size_t *bytes)
     (void)len;
     const Ctx *c = &x->c;
     const u64 S = (u64)c->nq * c->N, P = (u64)n * (n - 1) / 2;
-    u64 chunk = std::min<u64>(P, 64);
+    u64 chunk = std::min<u64>(P, (u64)c->tune.ks_chunk);
     *bytes = (P * S + chunk * ks_words_per_ct(c) + chunk * 2 * S) * 8;
+    return LC_OK;
+}
+
+int lc_set_tuning(lc_ctx *x, const char *name, int value)
+{
+    if (!x || !name) return LC_EINVAL;
+    Ctx *c = &x->c;
+    std::string k(name);
+    if (k == "pair_lanes") {
+        if (value != 8 && value != 16 && value != 32 && value != 64) return fail(c, LC_EINVAL, "pair_lanes: 8/16/32/64");
+        c->tune.pair_lanes = value;
+    } else if (k == "pair_ppt") {
+        if (value != 1 && value != 3 && value != 6) return fail(c, LC_EINVAL, "pair_ppt: 1/3/6");
+        c->tune.pair_ppt = value;
+    } else if (k == "ks_chunk") {
+        if (value < 1 || value > 256) return fail(c, LC_EINVAL, "ks_chunk: 1..256");
+        c->tune.ks_chunk = value;
+    } else {
+        return fail(c, LC_EINVAL, "unknown tuning parameter " + k);
+    }
     return LC_OK;
 }
 

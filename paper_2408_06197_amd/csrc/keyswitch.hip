@@ -66,32 +66,65 @@ struct KeySet {
 };
 
 // acc[b][k][l][j] = sum_t sum_d X_d[l][perm_t(j)] key_t[d][k][l][j]
+//
+// A lane owns one coefficient (l, j) of MAC_B ciphertexts: each key value is
+// read once and used for all MAC_B of them (the key of a block is read once per
+// MAC_B ciphertexts instead of once per ciphertext).  Products use the FP64
+// Barrett form (|x key| reduced to at most 0.875 q); the two accumulators per
+// ciphertext are reduced after every 8 products, so they stay below 8 q.
+constexpr int MAC_B = 8;
+
 __global__ void __launch_bounds__(KS_THREADS)
 mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, u64 *acc, u64 count)
 {
-    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over ne * N (one ciphertext per blockIdx.y)
-    u64 b = blockIdx.y;
-    if (e >= (u64)dp.ne * dp.N || b >= count) return;
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over ne * N
+    u64 b0 = (u64)blockIdx.y * MAC_B;
+    if (e >= (u64)dp.ne * dp.N) return;
     int l = (int)(e >> dp.log_n);
     u64 j = e & (dp.N - 1);
     const u64 NE = (u64)dp.ne * dp.N;
-    Split3 s0, s1;
-    split_zero(s0);
-    split_zero(s1);
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+    const int nb = (int)min<u64>(MAC_B, count - b0);
+    const bool own_limb = l < dp.nq;
+    const int own_digit = own_limb ? l / dp.alpha : -1;
+    double a0[MAC_B], a1[MAC_B];
+#pragma unroll
+    for (int b = 0; b < MAC_B; b++) a0[b] = a1[b] = 0.0;
+    int since = 0;
     for (int t = 0; t < ks.n; t++) {
         u64 src = ks.perm[t] ? ks.perm[t][j] : j;
         const u64 *key = ks.key[t];
         for (int d = 0; d < dp.dnum; d++) {
-            bool own = l < dp.nq && l / dp.alpha == d;
-            u64 v = own ? x[b * x_stride + (u64)l * dp.N + src]
-                        : raised[((b * dp.dnum + d) * dp.ne + l) * (u64)dp.N + src];
-            split_mac(s0, v, key[((u64)d * 2) * NE + e]);
-            split_mac(s1, v, key[((u64)d * 2 + 1) * NE + e]);
+            double k0 = u64_to_d(key[((u64)d * 2) * NE + e]);
+            double k1 = u64_to_d(key[((u64)d * 2 + 1) * NE + e]);
+            const bool own = d == own_digit;
+#pragma unroll
+            for (int b = 0; b < MAC_B; b++) {
+                if (b >= nb) break;
+                u64 bb = b0 + b;
+                u64 v = own ? x[bb * x_stride + (u64)l * dp.N + src]
+                            : raised[((bb * dp.dnum + d) * dp.ne + l) * (u64)dp.N + src];
+                double xv = u64_to_d(v);
+                a0[b] += mulmod_d(xv, k0, q, qinv);
+                a1[b] += mulmod_d(xv, k1, q, qinv);
+            }
+            if (++since == 8) {
+                since = 0;
+#pragma unroll
+                for (int b = 0; b < MAC_B; b++) {
+                    a0[b] = reduce_d(a0[b], q, qinv);
+                    a1[b] = reduce_d(a1[b], q, qinv);
+                }
+            }
         }
     }
-    const ModConst &mc = dp.mc[l];
-    acc[(b * 2) * NE + e] = reduce_split(s0, mc);
-    acc[(b * 2 + 1) * NE + e] = reduce_split(s1, mc);
+#pragma unroll
+    for (int b = 0; b < MAC_B; b++) {
+        if (b >= nb) break;
+        u64 bb = b0 + b;
+        acc[(bb * 2) * NE + e] = d_to_canonical(reduce_d(a0[b], q, qinv), q, qinv);
+        acc[(bb * 2 + 1) * NE + e] = d_to_canonical(reduce_d(a1[b], q, qinv), q, qinv);
+    }
 }
 
 // v[b][k][l][j] = BConv_{P->Q} of the (coefficient-domain) P limbs of acc.
@@ -158,9 +191,9 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
     for (int g = 0; g < ngroups; g++)
         if (groups[g].n < 1 || groups[g].n > 8) return fail(c, LC_EINVAL, "1..8 keys per hoisted group");
     const u64 per_ct = ks_words_per_ct(c);
-    u64 chunk = std::min<u64>(count, 64);
+    u64 chunk = std::min<u64>(count, (u64)c->tune.ks_chunk);
     if (c->ws_limit) chunk = std::max<u64>(1, std::min<u64>(chunk, c->ws_limit / (per_ct * 8)));
-    u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk);
+    u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk, s);
     if (!ws) return LC_ENOMEM;
     int rc;
     for (u64 b0 = 0; b0 < count; b0 += chunk) {
@@ -187,8 +220,8 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                 ks.key[t] = G.keys[t];
                 ks.perm[t] = G.perms[t];
             }
-            hipLaunchKernelGGL(mac_kernel, dim3(blocks_for((u64)ne * N), (u32)B), dim3(KS_THREADS), 0, s, c->dp, xb,
-                               x_stride, raised, ks, acc, B);
+            hipLaunchKernelGGL(mac_kernel, dim3(blocks_for((u64)ne * N), (u32)((B + MAC_B - 1) / MAC_B)),
+                               dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
             LC_HIP(c, hipGetLastError());
             if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
             hipLaunchKernelGGL(moddown_bconv_kernel, dim3(blocks_for(B * 2 * N)), dim3(KS_THREADS), 0, s, c->dp, acc,

@@ -26,6 +26,7 @@ struct DevParams {
     const u64 *tw, *tw_sh;    // [ne][N]: psi^brev(k) and Shoup companions
     const u64 *itw, *itw_sh;  // [ne][N]: inverses of the above
     const u64 *ninv, *ninv_sh;  // [ne]: N^-1 mod m
+    const double *twd, *itwd;   // [ne][N]: the twiddles above as doubles (FP64 butterflies)
     const u64 *up_inv, *up_inv_sh;  // [dnum][alpha]: (Q_d / q_a)^-1 mod q_a
     const u64 *up_fac;              // [dnum][alpha][ne]: (Q_d / q_a) mod m_l
     const u64 *dn_inv, *dn_inv_sh;  // [np]: (P / p_k)^-1 mod p_k
@@ -66,10 +67,21 @@ struct Ctx {
     u64 *sk2_ntt = nullptr;      // [nq][N]: s^2
     u64 *sk2_ntt_sh = nullptr;
 
-    // workspace: independent slots grown on demand
-    void *slot[8] = {};
-    size_t slot_bytes[8] = {};
+    // workspace: independent slots grown on demand, one set per stream so
+    // that work queued on different streams never shares scratch memory
+    struct Workspace {
+        void *slot[8] = {};
+        size_t bytes[8] = {};
+    };
+    std::map<hipStream_t, Workspace> ws;
     size_t ws_limit = 0;
+
+    // launch-shape tuning (lc_set_tuning)
+    struct Tuning {
+        int pair_lanes = 32;  // coefficients per workgroup of the pair-triple kernel
+        int pair_ppt = 6;     // pairs per lane (1, 3, 6 or 12)
+        int ks_chunk = 64;    // ciphertexts per key-switch batch
+    } tune;
     size_t table_bytes = 0, key_bytes = 0;
 };
 
@@ -86,9 +98,10 @@ int hip_fail(Ctx *c, hipError_t e, const char *what);
 // device memory owned by the context
 void *dev_alloc(Ctx *c, size_t bytes);
 enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5 };
-// Pointer to workspace slot `slot` of at least `bytes`; NULL (with ctx->err
-// set) if it cannot be allocated.  Growing a slot waits for the device.
-u64 *ws_get(Ctx *c, int slot, size_t bytes);
+// Pointer to workspace slot `slot` of stream `s` holding at least `bytes`;
+// NULL (with ctx->err set) if it cannot be allocated.  Growing a slot waits
+// for the work already queued on `s`.
+u64 *ws_get(Ctx *c, int slot, size_t bytes, hipStream_t s);
 
 // host-side parameter setup (params.cpp)
 int build_params(Ctx *c, const lc_params *prm);
@@ -124,7 +137,7 @@ int launch_tensor(Ctx *c, const u64 *a, const u64 *b, u64 *out3, u64 count, hipS
 int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, hipStream_t s);
 int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s);
 int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
-                        hipStream_t s);
+                        int accumulate, hipStream_t s);
 int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s);
 int launch_copy(Ctx *c, const u64 *src, u64 *dst, u64 words, hipStream_t s);
 

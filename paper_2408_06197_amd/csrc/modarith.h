@@ -37,6 +37,7 @@ __device__ __forceinline__ u64 mul_shoup(u64 x, u64 w, u64 wsh, u64 m) { return 
 // Per-modulus constants for the end of a split accumulation.
 struct ModConst {
     u64 m;
+    double qd, qinv;  // q and fl(1/q) for the FP64 Barrett form
     u64 c50, c50sh;  // 2^50 mod m and its Shoup companion
     u64 c25, c25sh;  // 2^25 mod m
     u64 one_sh;      // floor(2^64 / m): Shoup companion of 1 (Barrett reduction)
@@ -108,5 +109,50 @@ __device__ __forceinline__ u64 from_signed(int64_t v, const ModConst &c)
     u64 r = csub(mul_shoup_lazy((u64)(-(v + 1)), 1, c.one_sh, c.m), c.m);  // (-v-1) mod m
     return c.m - 1 - r;
 }
+
+// ---- FP64 Barrett form (NTT butterflies) ----------------------------------
+//
+// gfx950 runs FP64 FMA at full rate and 32-bit integer multiplies at about
+// half rate, so the NTT keeps its values as exactly-representable signed
+// integers in doubles while a pass runs.  For q < 2^50, |y| <= 4q, w < q:
+//   p = fl(y w),  e = fma(y, w, -p)       (y w = p + e exactly, |e| <= 2^-53 |p|)
+//   k = rint(p * fl(1/q))                  (Barrett quotient estimate, |k - yw/q| <= 2)
+//   r = fma(-k, q, p) + e                  (both steps exact: the values are
+//                                           integers of magnitude < 2^53)
+// gives r = y w - k q, an integer with |r| <= 2q.  reduce_d brings any |x| < 2^52
+// to |x| <= q/2 + 1 the same way.  Every quantity stays exact, so the canonical
+// residue read out at the end is the same as with integer arithmetic.
+#pragma clang fp contract(off)
+__device__ __forceinline__ double mulmod_d(double y, double w, double q, double qinv)
+{
+    double p = y * w;
+    double e = __fma_rn(y, w, -p);
+    double k = __builtin_rint(p * qinv);
+    return __fma_rn(-k, q, p) + e;
+}
+
+__device__ __forceinline__ double reduce_d(double x, double q, double qinv)
+{
+    double k = __builtin_rint(x * qinv);
+    return __fma_rn(-k, q, x);
+}
+
+// u64 residue (< 2^53) to double, exactly.
+__device__ __forceinline__ double u64_to_d(u64 v)
+{
+    return __fma_rn((double)(u32)(v >> 32), 4294967296.0, (double)(u32)v);
+}
+
+// integer-valued double with |x| <= 2q to the canonical residue in [0, q).
+__device__ __forceinline__ u64 d_to_canonical(double x, double q, double qinv)
+{
+    double r = reduce_d(x, q, qinv);   // |r| <= q/2 + 1
+    if (r < 0) r += q;
+    if (r >= q) r -= q;
+    u32 hi = (u32)(r * (1.0 / 4294967296.0));
+    u32 lo = (u32)__fma_rn(-(double)hi, 4294967296.0, r);
+    return ((u64)hi << 32) | lo;
+}
+#pragma clang fp contract(on)
 
 }  // namespace lc

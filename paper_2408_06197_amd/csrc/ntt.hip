@@ -132,11 +132,10 @@ __device__ __forceinline__ u32 lds_idx(u32 c, u32 a)
 }
 
 template <int LOG_S, bool INVERSE>
-__device__ __forceinline__ void ntt_round(u64 (&x)[16], bool top, u32 t, u64 hi, int s0, const u64 *tw,
-                                          const u64 *tws, u64 q)
+__device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 hi, int s0, const double *tw,
+                                          double q, double qinv)
 {
     constexpr int LB = LOG_S - 4;
-    const u64 q2 = 2 * q;
     // local stages of this round, in execution order
     int first = top ? 0 : 4, last = top ? 3 : LOG_S - 1;
 #pragma unroll
@@ -150,40 +149,43 @@ __device__ __forceinline__ void ntt_round(u64 (&x)[16], bool top, u32 t, u64 hi,
         for (int h = 0; h < 16; h++) {
             if (h & (1 << hb)) continue;
             u32 a1 = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
-            u64 ti = base + (a1 >> (LOG_S - sl));
-            u64 w = tw[ti], wsh = tws[ti];
-            u64 X = x[h], Y = x[h | (1 << hb)];
+            double w = tw[base + (a1 >> (LOG_S - sl))];
+            double X = x[h], Y = x[h | (1 << hb)];
+            // invariant: |X|, |Y| <= 2q on entry and exit
             if (!INVERSE) {
-                X = csub(X, q2);
-                u64 T = mul_shoup_lazy(Y, w, wsh, q);
+                double T = mulmod_d(Y, w, q, qinv);  // |T| <= 2q
+                X = reduce_d(X, q, qinv);            // |X| <= q/2 + 1
                 x[h] = X + T;
-                x[h | (1 << hb)] = X - T + q2;
+                x[h | (1 << hb)] = X - T;
             } else {
-                x[h] = csub(X + Y, q2);
-                x[h | (1 << hb)] = mul_shoup_lazy(X - Y + q2, w, wsh, q);
+                double S = reduce_d(X + Y, q, qinv);
+                x[h | (1 << hb)] = mulmod_d(X - Y, w, q, qinv);
+                x[h] = S;
             }
         }
     }
 }
 
+// first_: the pass reads uint64 residues (else doubles left by the other pass);
+// final_: the pass writes canonical uint64 residues (times N^-1 when inverse).
 template <int LOG_S, bool INVERSE, bool BLOCKS>
 __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
 {
     constexpr u32 S = 1u << LOG_S;
     constexpr int LB = LOG_S - 4;
     constexpr u32 TPC = S / 16;  // lanes per sub-transform
-    extern __shared__ u64 lds[];
+    extern __shared__ double lds[];
     u64 *poly;
     int mi;
     if (!poly_of_block(dp, pb, blockIdx.x, poly, mi)) return;
-    const u64 q = dp.mc[mi].m, q2 = 2 * q;
+    const double q = dp.mc[mi].qd, qinv = dp.mc[mi].qinv;
     const u32 tile = blockIdx.y;
     const u32 stride = dp.N >> (s0 + LOG_S);
     const u32 nthreads = blockDim.x;
     const u32 tid = threadIdx.x;
     const u32 nel = S * (u32)cols;
-    const u64 *tw = (INVERSE ? dp.itw : dp.tw) + (u64)mi * dp.N;
-    const u64 *tws = (INVERSE ? dp.itw_sh : dp.tw_sh) + (u64)mi * dp.N;
+    const double *tw = (INVERSE ? dp.itwd : dp.twd) + (u64)mi * dp.N;
+    const bool first_ = !final_;
     // tile geometry
     u64 hi_col = 0, lo0 = 0;
     if (!BLOCKS) {
@@ -191,18 +193,34 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         hi_col = tile / lo_tiles;
         lo0 = (u64)(tile % lo_tiles) * (u32)cols;
     }
-    // coalesced load into LDS
-    for (u32 e = tid; e < nel; e += nthreads) {
-        u32 a, c;
+    // coalesced load into LDS: every lane issues its eight 16-byte loads
+    // (element pairs e, e+1 with e even) before writing any of them
+    u64 v[16];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        u32 e = 2 * (tid + (u32)i * nthreads);
         u64 g;
-        if (BLOCKS) { c = e >> LOG_S; a = e & (S - 1); g = ((u64)tile * cols + c) * S + a; }
-        else { a = e / (u32)cols; c = e % (u32)cols; g = (hi_col * S + a) * stride + lo0 + c; }
-        lds[lds_idx<LOG_S>(c, a)] = poly[g];
+        if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
+        else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
+        ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(poly + g);
+        v[2 * i] = p2.x;
+        v[2 * i + 1] = p2.y;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        u32 e = 2 * (tid + (u32)i * nthreads);
+        u32 a, c;
+        if (BLOCKS) { c = e >> LOG_S; a = e & (S - 1); }
+        else { a = e / (u32)cols; c = e % (u32)cols; }
+        // BLOCKS: (c, a), (c, a+1); columns: (c, a), (c+1, a)
+        u32 i0 = lds_idx<LOG_S>(c, a), i1 = BLOCKS ? lds_idx<LOG_S>(c, a + 1) : lds_idx<LOG_S>(c + 1, a);
+        lds[i0] = first_ ? u64_to_d(v[2 * i]) : __longlong_as_double((long long)v[2 * i]);
+        lds[i1] = first_ ? u64_to_d(v[2 * i + 1]) : __longlong_as_double((long long)v[2 * i + 1]);
     }
     __syncthreads();
     const u32 c = tid / TPC, t = tid % TPC;
     const u64 hi = BLOCKS ? ((u64)tile * cols + c) : hi_col;
-    u64 x[16];
+    double x[16];
 #pragma unroll
     for (int r = 0; r < 2; r++) {
         bool top = INVERSE ? (r == 1) : (r == 0);
@@ -211,7 +229,7 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
             u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
             x[h] = lds[lds_idx<LOG_S>(c, a)];
         }
-        ntt_round<LOG_S, INVERSE>(x, top, t, hi, s0, tw, tws, q);
+        ntt_round<LOG_S, INVERSE>(x, top, t, hi, s0, tw, q, qinv);
 #pragma unroll
         for (int h = 0; h < 16; h++) {
             u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
@@ -219,18 +237,29 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         }
         __syncthreads();
     }
-    const u64 ni = dp.ninv[mi], nish = dp.ninv_sh[mi];
-    for (u32 e = tid; e < nel; e += nthreads) {
+    const double ni = (double)dp.ninv[mi];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        u32 e = 2 * (tid + (u32)i * nthreads);
         u32 a, cc;
         u64 g;
         if (BLOCKS) { cc = e >> LOG_S; a = e & (S - 1); g = ((u64)tile * cols + cc) * S + a; }
         else { a = e / (u32)cols; cc = e % (u32)cols; g = (hi_col * S + a) * stride + lo0 + cc; }
-        u64 v = lds[lds_idx<LOG_S>(cc, a)];
+        double d0 = lds[lds_idx<LOG_S>(cc, a)];
+        double d1 = BLOCKS ? lds[lds_idx<LOG_S>(cc, a + 1)] : lds[lds_idx<LOG_S>(cc + 1, a)];
+        ulonglong2 o;
         if (final_) {
-            if (INVERSE) v = mul_shoup(v, ni, nish, q);
-            else v = csub(csub(v, q2), q);
+            if (INVERSE) {
+                d0 = mulmod_d(d0, ni, q, qinv);
+                d1 = mulmod_d(d1, ni, q, qinv);
+            }
+            o.x = d_to_canonical(d0, q, qinv);
+            o.y = d_to_canonical(d1, q, qinv);
+        } else {
+            o.x = (u64)__double_as_longlong(d0);
+            o.y = (u64)__double_as_longlong(d1);
         }
-        poly[g] = v;
+        *reinterpret_cast<ulonglong2 *>(poly + g) = o;
     }
 }
 

@@ -110,43 +110,75 @@ int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, 
 }
 
 // out[k][comp][l][j] = sum_i cts[i][k][comp][l][j] * masks[i][l][j]
+// Two adjacent coefficients per lane (16-byte accesses), four clients' loads
+// in flight; FP64 Barrett products (|r| <= 0.875 q) summed with a reduction
+// after at most 8 clients.
 __global__ void __launch_bounds__(EW_THREADS)
-masked_sum_kernel(DevParams dp, const u64 *cts, int n, int len, const u64 *masks, u64 *out, u64 total)
+masked_sum_kernel(DevParams dp, const u64 *cts, int n, int len, const u64 *masks, u64 *out, u64 total2)
 {
-    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over len * 2 * nq * N
-    if (e >= total) return;
+    u64 e2 = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over len * 2 * nq * N / 2
+    if (e2 >= total2) return;
+    u64 e = 2 * e2;
     u64 S = (u64)dp.nq << dp.log_n;
     u64 r = e % S;
     int l = (int)(r >> dp.log_n);
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     u64 client_stride = (u64)len * 2 * S;
-    Split3 acc;
-    split_zero(acc);
-    for (int i = 0; i < n; i++) split_mac(acc, cts[(u64)i * client_stride + e], masks[(u64)i * S + r]);
-    out[e] = reduce_split(acc, dp.mc[l]);
+    double a0 = 0.0, a1 = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 4) {
+        ulonglong2 c2[4], m2[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int i = min(i0 + u, n - 1);
+            c2[u] = *reinterpret_cast<const ulonglong2 *>(cts + (u64)i * client_stride + e);
+            m2[u] = *reinterpret_cast<const ulonglong2 *>(masks + (u64)i * S + r);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (i0 + u < n) {
+                a0 += mulmod_d(u64_to_d(c2[u].x), u64_to_d(m2[u].x), q, qinv);
+                a1 += mulmod_d(u64_to_d(c2[u].y), u64_to_d(m2[u].y), q, qinv);
+            }
+        }
+        if ((i0 & 7) == 4 || i0 + 4 >= n) {  // at most 8 products between reductions
+            a0 = reduce_d(a0, q, qinv);
+            a1 = reduce_d(a1, q, qinv);
+        }
+    }
+    ulonglong2 o;
+    o.x = d_to_canonical(reduce_d(a0, q, qinv), q, qinv);
+    o.y = d_to_canonical(reduce_d(a1, q, qinv), q, qinv);
+    *reinterpret_cast<ulonglong2 *>(out + e) = o;
 }
 
 int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s)
 {
-    u64 total = (u64)len * 2 * c->nq * c->N;
-    if (!total) return LC_OK;
-    hipLaunchKernelGGL(masked_sum_kernel, grid_for(total, EW_THREADS), dim3(EW_THREADS), 0, s, c->dp, cts, n, len,
-                       masks, out, total);
+    u64 total2 = (u64)len * c->nq * c->N;  // pairs of coefficients (N is even)
+    if (!total2) return LC_OK;
+    hipLaunchKernelGGL(masked_sum_kernel, grid_for(total2, EW_THREADS), dim3(EW_THREADS), 0, s, c->dp, cts, n, len,
+                       masks, out, total2);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }
 
 // ---- fused subtract / square / lazy accumulate over all pairs --------------
 //
-// Workgroup = (coefficient tile of T lanes, limb l, chunk of pairs).  KB
-// packed ciphertexts at a time, the tiles of all n clients (both components)
-// are staged in LDS and every pair of the chunk reads them from there; each
-// lane keeps PPT pairs' accumulators (three split sums per triple component,
-// 18 VGPRs per pair) in registers across all k, and reduces once at the end.
+// Workgroup = (tile of T coefficients, limb l, chunk of pairs).  KB packed
+// ciphertexts at a time, the tiles of all n clients (both components) are
+// staged in LDS once -- as exact doubles -- and every pair of the chunk reads
+// them from there.  A lane owns one coefficient of PPT pairs and keeps their
+// triple accumulators in registers across all k.  T and PPT are tuning
+// parameters (lc_set_tuning); the defaults come from measurements on MI355X.
+//
+// Arithmetic is the FP64 Barrett form of modarith.h: differences x = a - b
+// lie in (-q, q); each product comes back as an integer r with |r| <= 0.875 q;
+// the accumulators (|acc| <= q/2 + 1 after a reduction) take at most
+// KB * 1.75 q <= 7 q before the next reduction, so they stay below 2^53 and
+// every value is exact.  The canonical residue is taken once at the end.
 
-constexpr int PT_T = 16;        // coefficients per workgroup
 constexpr int PT_MAXN = 64;     // clients per call
-constexpr int PT_PPT = 3;       // pairs per lane
-constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
+constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier (at most)
+constexpr size_t PT_LDS = 64 * 1024;
 
 __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
 {
@@ -159,95 +191,114 @@ __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
     j = row + 1 + (p - base);
 }
 
-template <int PPT, int KB>
+__host__ __device__ inline int pair_index(int n, int i, int j) { return i * (2 * n - i - 1) / 2 + (j - i - 1); }
+
+template <int PPT>
 __global__ void __launch_bounds__(1024)
 pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int P, u64 *d01, u64 d01_stride,
-                    u64 *d2, u64 d2_stride)
+                    u64 *d2, u64 d2_stride, int KB, int accumulate)
 {
-    extern __shared__ u64 tile[];  // [KB][n][2][T]
-    const int T = blockDim.x;      // coefficient lanes
-    const int G = blockDim.y;      // pair groups
+    extern __shared__ double tile[];  // [KB][n][2][T]
+    const int T = blockDim.x;         // coefficient lanes
+    const int G = blockDim.y;         // pair groups
     const int lane = threadIdx.x, g = threadIdx.y;
     const int tid = g * T + lane;
     const int nthreads = T * G;
     const int l = blockIdx.y;
     const u64 N = dp.N;
     const u64 S = (u64)dp.nq * N;
-    const ModConst mc = dp.mc[l];
-    const u64 q = mc.m;
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     const int per_k = n * 2 * T;
 
-    int offa[PPT], offb[PPT], pp[PPT];
-    bool live[PPT];
+    // pair r of this lane is p = pbase + r G; its two clients' LDS offsets
+    // are packed into one register
+    const int pbase = blockIdx.z * (G * PPT) + g;
+    int offs[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
-        int p = blockIdx.z * (G * PPT) + r * G + g;
-        live[r] = p < P;
-        pp[r] = p;
-        int i = 0, j = 1;
-        if (live[r]) pair_of_index(p, n, i, j);
-        offa[r] = (i * 2) * T + lane;
-        offb[r] = (j * 2) * T + lane;
+        int p = pbase + r * G, i = 0, j = 1;
+        if (p < P) pair_of_index(p, n, i, j);
+        offs[r] = ((i * 2) * T + lane) | (((j * 2) * T + lane) << 16);
     }
-    Split3 acc[PPT][3];
+    double acc[PPT][3];
 #pragma unroll
-    for (int r = 0; r < PPT; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) split_zero(acc[r][c]);
+    for (int r = 0; r < PPT; r++) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
 
     const u64 client_stride = (u64)len * 2 * S;
     const u64 off = (u64)l * N + (u64)blockIdx.x * T;
     for (int k0 = 0; k0 < len; k0 += KB) {
         const int kb = min(KB, len - k0);
         for (int idx = tid; idx < kb * per_k; idx += nthreads) {
-            int kk = idx / per_k, rem = idx - kk * per_k;
-            int t = rem % T, ic = rem / T;  // ic = i * 2 + comp
-            int i = ic >> 1, comp = ic & 1;
-            tile[idx] = cts[(u64)i * client_stride + (u64)(k0 + kk) * 2 * S + (u64)comp * S + off + t];
+            int row = idx / T, t = idx - row * T;
+            int kk = row / (2 * n), rr = row - kk * 2 * n;  // rr = client * 2 + comp
+            tile[idx] = u64_to_d(cts[(u64)(rr >> 1) * client_stride + (u64)(k0 + kk) * 2 * S + (u64)(rr & 1) * S +
+                                     off + t]);
         }
         __syncthreads();
         for (int kk = 0; kk < kb; kk++) {
-            const u64 *tl = tile + kk * per_k;
+            const double *tl = tile + kk * per_k;
 #pragma unroll
             for (int r = 0; r < PPT; r++) {
-                if (!live[r]) continue;
-                u64 x0 = sub_mod(tl[offa[r]], tl[offb[r]], q);
-                u64 x1 = sub_mod(tl[offa[r] + T], tl[offb[r] + T], q);
-                split_sq(acc[r][0], x0);
-                split_mac(acc[r][1], x0, x1);
-                split_sq(acc[r][2], x1);
+                if (pbase + r * G < P) {
+                    const int oa = offs[r] & 0xffff, ob = offs[r] >> 16;
+                    double x0 = tl[oa] - tl[ob];
+                    double x1 = tl[oa + T] - tl[ob + T];
+                    double m = mulmod_d(x0, x1, q, qinv);
+                    acc[r][0] += mulmod_d(x0, x0, q, qinv);
+                    acc[r][1] += m + m;
+                    acc[r][2] += mulmod_d(x1, x1, q, qinv);
+                }
             }
+        }
+#pragma unroll
+        for (int r = 0; r < PPT; r++) {
+            acc[r][0] = reduce_d(acc[r][0], q, qinv);
+            acc[r][1] = reduce_d(acc[r][1], q, qinv);
+            acc[r][2] = reduce_d(acc[r][2], q, qinv);
         }
         __syncthreads();
     }
     const u64 o = (u64)l * N + (u64)blockIdx.x * T + lane;
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
-        if (!live[r]) continue;
-        u64 v0 = reduce_split_sq(acc[r][0], mc);
-        u64 v1 = reduce_split(acc[r][1], mc);
-        v1 = add_mod(v1, v1, q);
-        u64 v2 = reduce_split_sq(acc[r][2], mc);
-        d01[(u64)pp[r] * d01_stride + o] = v0;
-        d01[(u64)pp[r] * d01_stride + S + o] = v1;
-        d2[(u64)pp[r] * d2_stride + o] = v2;
+        const u64 p = (u64)(pbase + r * G);
+        if (p < (u64)P) {
+            u64 *o0 = d01 + p * d01_stride + o, *o1 = o0 + S, *o2 = d2 + p * d2_stride + o;
+            if (accumulate) {  // |acc| <= q/2 + 1, previous value in [0, q): the sum stays within 2q
+                acc[r][0] += u64_to_d(*o0);
+                acc[r][1] += u64_to_d(*o1);
+                acc[r][2] += u64_to_d(*o2);
+            }
+            *o0 = d_to_canonical(acc[r][0], q, qinv);
+            *o1 = d_to_canonical(acc[r][1], q, qinv);
+            *o2 = d_to_canonical(acc[r][2], q, qinv);
+        }
     }
 }
 
 int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
-                        hipStream_t s)
+                        int accumulate, hipStream_t s)
 {
     if (n < 2 || n > PT_MAXN) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
-    if (len < 1 || len > 4096) return fail(c, LC_EINVAL, "len must lie in [1, 4096]");
+    if (len < 1) return fail(c, LC_EINVAL, "len must be >= 1");
     int P = n * (n - 1) / 2;
-    int T = (int)std::min<u64>(PT_T, c->N);
-    int groups_needed = (P + PT_PPT - 1) / PT_PPT;
-    int G = std::min(groups_needed, 1024 / T);
-    int chunks = (P + G * PT_PPT - 1) / (G * PT_PPT);
+    int ppt = c->tune.pair_ppt, T = c->tune.pair_lanes;
+    if (P <= 64) ppt = 1;  // few pairs: one per lane
+    T = (int)std::min<u64>((u64)T, c->N);
+    int G = std::max(1, std::min((P + ppt - 1) / ppt, 1024 / T));
+    int chunks = (P + G * ppt - 1) / (G * ppt);
     dim3 grid((u32)(c->N / T), (u32)c->nq, (u32)chunks), block(T, G);
-    size_t lds = (size_t)PT_KB * n * 2 * T * sizeof(u64);
-    hipLaunchKernelGGL((pair_triples_kernel<PT_PPT, PT_KB>), grid, block, lds, s, c->dp, cts, n, len, P, d01,
-                       d01_stride, d2, d2_stride);
+    size_t per_k = (size_t)n * 2 * T * sizeof(double);
+    int kb = (int)std::max<size_t>(1, std::min<size_t>(PT_KB, PT_LDS / per_k));
+    size_t lds = (size_t)kb * per_k;
+    switch (ppt) {
+    case 1: hipLaunchKernelGGL((pair_triples_kernel<1>), grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride,
+                               d2, d2_stride, kb, accumulate); break;
+    case 3: hipLaunchKernelGGL((pair_triples_kernel<3>), grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride,
+                               d2, d2_stride, kb, accumulate); break;
+    default: hipLaunchKernelGGL((pair_triples_kernel<6>), grid, block, lds, s, c->dp, cts, n, len, P, d01,
+                                d01_stride, d2, d2_stride, kb, accumulate); break;
+    }
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }
@@ -267,7 +318,7 @@ sumdis_kernel(DevParams dp, const u64 *dist, int n, u64 *sumdis, u64 total)
     for (int j = 0; j < n; j++) {
         if (j == i) continue;
         int a = i < j ? i : j, b = i < j ? j : i;
-        int p = a * (2 * n - a - 1) / 2 + (b - a - 1);
+        int p = pair_index(n, a, b);
         acc = add_mod(acc, dist[(u64)p * S2 + r], q);
     }
     sumdis[e] = acc;

@@ -192,11 +192,14 @@ int build_params(Ctx *c, const lc_params *prm)
         mc[l].c25 = (u64)(((u128)1 << 25) % m);
         mc[l].c25sh = shoup_of(mc[l].c25, m);
         mc[l].one_sh = shoup_of(1, m);
+        mc[l].qd = (double)m;
+        mc[l].qinv = 1.0 / (double)m;
     }
     d.mc = upload(c, mc);
 
     // twiddles: tw[l][k] = psi^brev(k) for k in [0, N); itw = inverses
     std::vector<u64> tw(ne * N), tws(ne * N), itw(ne * N), itws(ne * N), ninv(ne), ninvs(ne);
+    std::vector<double> twd(ne * N), itwd(ne * N);
     for (int l = 0; l < ne; l++) {
         u64 m = c->mod[l], psi = c->psi[l], ipsi = invm(psi, m);
         std::vector<u64> pw(N), ipw(N);
@@ -211,6 +214,8 @@ int build_params(Ctx *c, const lc_params *prm)
             tws[l * N + k] = shoup_of(pw[r], m);
             itw[l * N + k] = ipw[r];
             itws[l * N + k] = shoup_of(ipw[r], m);
+            twd[l * N + k] = (double)pw[r];
+            itwd[l * N + k] = (double)ipw[r];
         }
         ninv[l] = invm(N % m, m);
         ninvs[l] = shoup_of(ninv[l], m);
@@ -221,6 +226,8 @@ int build_params(Ctx *c, const lc_params *prm)
     d.itw_sh = upload(c, itws);
     d.ninv = upload(c, ninv);
     d.ninv_sh = upload(c, ninvs);
+    d.twd = upload(c, twd);
+    d.itwd = upload(c, itwd);
 
     // ModUp constants per digit
     std::vector<u64> upi(dnum * alpha, 0), upis(dnum * alpha, 0), upf((size_t)dnum * alpha * ne, 0);
@@ -280,6 +287,7 @@ int build_params(Ctx *c, const lc_params *prm)
     c->cdt_host = cdt;
 
     if (c->device < 0) return LC_OK;
+    if (!d.twd || !d.itwd) return fail(c, LC_ENOMEM, "could not upload parameter tables");
     if (!d.mc || !d.tw || !d.tw_sh || !d.itw || !d.itw_sh || !d.ninv || !d.ninv_sh || !d.up_inv || !d.up_inv_sh ||
         !d.up_fac || !d.dn_inv || !d.dn_inv_sh || !d.dn_fac || !d.pinv || !d.pinv_sh || !d.pmod || !d.cdt)
         return fail(c, LC_ENOMEM, "could not upload parameter tables");

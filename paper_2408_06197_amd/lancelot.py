@@ -66,11 +66,14 @@ _SIGS = {
     "lc_mul_plain": [VP, VP, VP, VP, SZ, VP],
     "lc_masked_sum": [VP, VP, INT, INT, VP, VP, VP],
     "lc_pair_triples": [VP, VP, INT, INT, VP, VP],
+    "lc_pair_triples_acc": [VP, VP, INT, INT, VP, VP],
+    "lc_pairwise_finish": [VP, VP, INT, PINT, INT, VP, VP, VP],
     "lc_pairwise_sqdist": [VP, VP, INT, INT, PINT, INT, VP, VP, VP],
     "lc_ntt_fwd": [VP, VP, SZ, INT, INT, VP],
     "lc_ntt_inv": [VP, VP, SZ, INT, INT, VP],
     "lc_workspace_query": [VP, INT, INT, _c.POINTER(SZ)],
     "lc_set_workspace_limit": [VP, SZ],
+    "lc_set_tuning": [VP, _c.c_char_p, INT],
 }
 
 _lib = None
@@ -314,6 +317,21 @@ class Context:
         self._check(lib().lc_pair_triples(self._h, _ptr(cts), n, ln, _ptr(out), _stream(stream)))
         return out
 
+    def pair_triples_acc(self, cts, triples, stream=None):
+        n, ln = cts.shape[0], cts.shape[1]
+        self._check(lib().lc_pair_triples_acc(self._h, _ptr(cts), n, ln, _ptr(triples), _stream(stream)))
+        return triples
+
+    def pairwise_finish(self, triples, n, plan=None, sumdis=False, out=None, sumdis_out=None, stream=None):
+        P = n * (n - 1) // 2
+        out = self.empty(P, 2, self.nq, self.N) if out is None else out
+        if sumdis and sumdis_out is None:
+            sumdis_out = self.empty(n, 2, self.nq, self.N)
+        pa, nb = (None, 0) if plan is None else _ints(plan)
+        self._check(lib().lc_pairwise_finish(self._h, _ptr(triples), n, pa, nb, _ptr(out),
+                                             _ptr(sumdis_out) if sumdis else None, _stream(stream)))
+        return (out, sumdis_out) if sumdis else out
+
     def pairwise_sqdist(self, cts, plan=None, sumdis=False, out=None, sumdis_out=None, stream=None):
         n, ln = cts.shape[0], cts.shape[1]
         P = n * (n - 1) // 2
@@ -345,6 +363,9 @@ class Context:
         b = SZ()
         self._check(lib().lc_workspace_query(self._h, n, len_, _c.byref(b)))
         return b.value
+
+    def set_tuning(self, name, value):
+        self._check(lib().lc_set_tuning(self._h, name.encode(), int(value)))
 
     def set_workspace_limit(self, nbytes):
         self._check(lib().lc_set_workspace_limit(self._h, nbytes))

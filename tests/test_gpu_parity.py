@@ -252,6 +252,56 @@ def test_pairwise_pipeline_bitexact(torch, L, oracle_mod, w):
     assert np.allclose(got, fp64_dists(upd), rtol=1e-3)
 
 
+@pytest.mark.parametrize("n,ln", [(40, 3), (64, 2), (13, 9)])
+def test_pair_triples_many_clients(torch, L, oracle_mod, n, ln):
+    """Pair chunking across workgroups and the LDS staging cap (40 and 64
+    clients), ragged staging of packed ciphertexts (9 = 2 * 4 + 1)."""
+    O = oracle_mod
+    prm = (5, (50, 45, 40), (50,))
+    ctx = L.Context(*prm, device=0)
+    ora = O.Oracle(*prm)
+    cts = synth.uniform_residues(31 + n, ctx.q, (n, ln, 2, ctx.N))
+    got = down(ctx.pair_triples(up(torch, cts)))
+    P = n * (n - 1) // 2
+    p = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if p % 7 == 0 or p == P - 1:
+                assert np.array_equal(got[p], ora.pair_triple(cts, i, j)), (i, j)
+            p += 1
+
+
+def test_chunked_triples_and_finish(torch, L, oracle_mod):
+    """Streaming the packed ciphertexts in chunks of k (accumulating triples)
+    then finishing gives the same bits as the one-shot pipeline and the oracle;
+    the same work on two streams at once gives the same bits again."""
+    O = oracle_mod
+    w = TINY_W5
+    ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    steps = ora0.rotsum_steps(w.rot_plan)
+    ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
+    upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
+    res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps], want_triples=True)
+    g = up(torch, cts)
+    n, ln = cts.shape[:2]
+    P = n * (n - 1) // 2
+    trip = torch.zeros((P, 3, ctx.nq, ctx.N), dtype=torch.int64, device="cuda")
+    for k0 in range(0, ln, 1):  # one packed ciphertext per chunk
+        ctx.pair_triples_acc(g[:, k0:k0 + 1].contiguous(), trip)
+    assert np.array_equal(down(trip), res["triples"])
+    dist, sd = ctx.pairwise_finish(trip, n, plan=list(w.rot_plan), sumdis=True)
+    assert np.array_equal(down(dist), res["dist"])
+    assert np.array_equal(down(sd), res["sumdis"])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for st in (s1, s2):
+        with torch.cuda.stream(st):
+            outs.append(ctx.pairwise_sqdist(g, plan=list(w.rot_plan), stream=st))
+    torch.cuda.synchronize()
+    for o in outs:
+        assert np.array_equal(down(o), res["dist"])
+
+
 def test_cfg2_sampled_pairs(torch, L, oracle_mod):
     """N=2^14, 8 limbs, 10 clients x 13 ciphertexts (ragged last one): all 45
     distances decrypt to FP64 within 1e-4; three pairs are bit-exact against

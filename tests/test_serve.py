@@ -1,0 +1,135 @@
+"""Serving form: admission logic on the CPU (fake executor and clock), and on
+the GPU the continuous-batching loop -- each round's distance ciphertexts
+are bit-identical whether the round runs alone or in a mix with others, and
+decrypt to the FP64 distances of the updates they encode."""
+import numpy as np
+import pytest
+
+from paper_2408_06197_amd import serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-4)
+
+
+class FakeExecutor:
+    """Each round takes `work` seconds of fake time once admitted."""
+
+    def __init__(self, clock, work):
+        self.clock, self.work = clock, work
+        self.started, self.max_active, self.active = [], 0, 0
+
+    def start(self, spec):
+        self.started.append((spec.rid, self.clock()))
+        self.active += 1
+        self.max_active = max(self.max_active, self.active)
+        return (spec, self.clock() + self.work(spec))
+
+    def poll(self, h):
+        return self.clock() >= h[1]
+
+    def finish(self, h):
+        self.active -= 1
+        return h[0].rid
+
+
+CH = {"a": serve.ChainInfo("a", 14, 8, 2, 40), "b": serve.ChainInfo("b", 16, 24, 4, 40)}
+
+
+def test_footprint_formula():
+    ch = CH["b"]
+    # 20 clients x 11.2M dims at N=2^16, 64-ciphertext chunks
+    fp = serve.round_footprint(ch, 20, 11_200_000, 64)
+    S = 24 * 65536 * 8
+    assert fp == 20 * 64 * (2 * S + 65536 * 8) + 190 * 6 * S
+
+
+def test_admission_respects_slots_and_budget():
+    clock = FakeClock()
+    specs = serve.make_stream(60, rate=50.0, chains=["a", "b"], seed=5, dims=(100_000, 1_000_000))
+    budget = max(serve.round_footprint(CH[s.chain], s.n, s.dim, 64) for s in specs) * 2
+    sch = serve.Scheduler(CH, budget, slots=3, k_chunk=64)
+    ex = FakeExecutor(clock, lambda s: 0.01 * s.n)
+    seen_used = []
+    orig = ex.start
+
+    def start(spec):
+        seen_used.append(sch.used)
+        return orig(spec)
+
+    ex.start = start
+    rec = sch.run(specs, ex, clock=clock, sleep=clock.sleep)
+    assert sorted(rec) == list(range(60))
+    assert ex.max_active <= 3
+    assert max(seen_used) <= budget
+    # arrival order is kept and nothing starts before it arrives
+    starts = [rid for rid, _ in ex.started]
+    assert starts == sorted(starts)
+    for r in rec.values():
+        assert r["admit"] >= r["arrival"] - 1e-9 and r["done"] > r["admit"]
+    st = serve.latency_stats(rec)
+    assert st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_round_larger_than_budget_is_refused():
+    sch = serve.Scheduler(CH, budget_bytes=1 << 20, slots=2, k_chunk=64)
+    spec = serve.RoundSpec(0, 0.0, "b", 40, 11_200_000, 4, "flip5", 1)
+    with pytest.raises(ValueError):
+        sch.can_admit(spec)
+
+
+def test_stream_draws():
+    specs = serve.make_stream(500, rate=2.0, chains=["a", "b"])
+    assert len(specs) == 500
+    assert {s.n for s in specs} == {5, 10, 20, 40}
+    assert {s.dim for s in specs} == {100_000, 1_000_000, 11_200_000}
+    assert all(1 <= s.n_byz <= max(1, round(0.2 * s.n)) for s in specs)
+    gaps = np.diff([s.arrival for s in specs])
+    assert np.all(gaps >= 0) and abs(gaps.mean() - 0.5) < 0.1
+
+
+@pytest.mark.gpu
+def test_alone_equals_mix_and_decrypts():
+    import torch
+    from paper_2408_06197_amd import lancelot as L
+
+    chains = {"s": serve.ChainInfo("s", 6, 4, 2, 35), "t": serve.ChainInfo("t", 7, 3, 1, 30)}
+    bits = {"s": ((50, 45, 45, 45), (50, 50)), "t": ((50, 45, 45), (50,))}
+    contexts, pools, plans = {}, {}, {}
+    for name, ch in chains.items():
+        qb, pb = bits[name]
+        kgc = L.Context(ch.log_n, qb, pb, device=0, role=L.ROLE_KGC)
+        srv = L.Context(ch.log_n, qb, pb, device=0, role=L.ROLE_SERVER)
+        plan = [2] * ((ch.log_n - 1) // 2) + [1] * ((ch.log_n - 1) % 2)
+        kgc.keygen(7)
+        kgc.keygen_rotation(7, kgc.rotsum_steps(plan))
+        kgc.keys_share(srv)
+        contexts[name] = (kgc, srv)
+        plans[name] = plan
+        pools[name] = serve.PlaintextPool(torch, srv, size=16, std=0.01, seed=11, scale=2.0 ** ch.scale_log2)
+    specs = serve.make_stream(8, rate=0.0, chains=["s", "t"], seed=9, clients=(2, 3, 5), dims=(40, 100, 300))
+    budget = 1 << 30
+
+    def run(sp, slots):
+        ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=2, streams=slots)
+        return serve.Scheduler(chains, budget, slots=slots, k_chunk=2).run(sp, ex)
+
+    alone = {}
+    for sp in specs:
+        alone.update(run([sp], 1))
+    mixed = run(specs, 4)
+    for rid, r in mixed.items():
+        a = alone[rid]["result"]["dist_ct"].cpu().numpy()
+        b = r["result"]["dist_ct"].cpu().numpy()
+        assert np.array_equal(a, b), rid
+        sp = specs[rid]
+        ref = serve.reference_distances(sp, pools[sp.chain], chains[sp.chain].n_ct(sp.dim))
+        got = r["result"]["distances"]
+        assert np.allclose(got, ref, rtol=1e-3), (rid, got, ref)
