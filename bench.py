@@ -25,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # FP64 lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz (78.6 TFLOP/s)
+A2_OPS_PER_UPDATE = 23
 
 
 def log(*a):
@@ -45,6 +46,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     p.add_argument("--oracle-cts", type=int, default=4, help="packed ciphertexts in the oracle's sample pair")
     p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
+    p.add_argument("--no-graph", dest="graph", action="store_false", default=True,
+                   help="time eager launches instead of a captured HIP graph")
     p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
                    help="also run the serving form: ROUNDS Poisson-arriving aggregation rounds")
     p.add_argument("--serve-slots", type=int, default=4)
@@ -91,10 +94,11 @@ def ntt_roofline(torch, srv, batch):
             "transform_ms_per_limb_poly": ms / npoly}
 
 
-def cpu_baseline(w, plan, n_cts):
-    """The oracle on the host cores: one client pair with n_cts packed
-    ciphertexts (tensor phase), one relinearization and the full rotate-and-
-    sum; scaled to the full pair (LEN ciphertexts) and reported as distances/s."""
+def cpu_baseline(w, plan, n_cts, min_seconds=12.0):
+    """The oracle on the host cores: client pairs (0, n-1), (1, n-2), ... each
+    with n_cts packed ciphertexts in the tensor phase (scaled linearly to the
+    full LEN), one relinearization and the full rotate-and-sum, until at least
+    min_seconds of oracle time; reported as distances/s."""
     from oracle import oracle as O
     import synth
 
@@ -104,25 +108,32 @@ def cpu_baseline(w, plan, n_cts):
     pk = ora.pk(seed, s)
     rlk = ora.relin_key(seed, s)
     rks = [ora.rot_key(seed, s, k) for k in ora.rotsum_steps(plan)]
-    upd = synth.client_updates(w, clients=[0, w.n_clients - 1])
     scale = 2.0 ** w.scale_log2
     k = min(n_cts, w.n_ct)
-    m = np.stack([np.stack([O.encode(c, w.log_n, scale) for c in synth.pack(u, w.slots)[:k]]) for u in upd])
-    cts = ora.encrypt(seed + 1, 0, m.reshape(2 * k, w.N), pk).reshape(2, k, 2, ora.nq, w.N)
-    t0 = time.perf_counter()
-    tri = ora.pair_triple(cts, 0, 1)
-    t1 = time.perf_counter()
-    d = ora.relin(tri, rlk)
-    t2 = time.perf_counter()
-    ora.rotate_sum(d, plan, rks)
-    t3 = time.perf_counter()
-    per_pair = (t1 - t0) * w.n_ct / k + (t3 - t1)
+    per_pair, spent, pairs = [], 0.0, []
+    for a in range(w.n_clients // 2):
+        b = w.n_clients - 1 - a
+        upd = synth.client_updates(w, clients=[a, b])
+        m = np.stack([np.stack([O.encode(c, w.log_n, scale) for c in synth.pack(u, w.slots)[:k]]) for u in upd])
+        cts = ora.encrypt(seed + 1, 0, m.reshape(2 * k, w.N), pk).reshape(2, k, 2, ora.nq, w.N)
+        t0 = time.perf_counter()
+        tri = ora.pair_triple(cts, 0, 1)
+        t1 = time.perf_counter()
+        d = ora.relin(tri, rlk)
+        ora.rotate_sum(d, plan, rks)
+        t3 = time.perf_counter()
+        per_pair.append((t1 - t0) * w.n_ct / k + (t3 - t1))
+        spent += t3 - t0
+        pairs.append((a, b))
+        if spent >= min_seconds:
+            break
+    sec = float(np.mean(per_pair))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / per_pair, "unit": "client-pair distances/s", "cores": cores, "kind": "oracle",
-            "sample": "one pair (clients 0, %d): tensor phase over %d of %d packed ciphertexts scaled x%.2f, plus "
-                      "1 relinearization and %d-block rotate-and-sum measured whole; oracle time %.1f s"
-                      % (w.n_clients - 1, k, w.n_ct, w.n_ct / k, len(plan), t3 - t0),
-            "seconds_per_pair": per_pair, "tensor_s": t1 - t0, "relin_s": t2 - t1, "rotsum_s": t3 - t2}
+    return {"value": 1.0 / sec, "unit": "client-pair distances/s", "cores": cores, "kind": "oracle",
+            "sample": "%d client pairs %s: tensor phase over %d of %d packed ciphertexts scaled x%.2f, plus one "
+                      "relinearization and the rotate-and-sum (plan %s) measured whole; %.1f s of oracle time"
+                      % (len(pairs), pairs, k, w.n_ct, w.n_ct / k, ",".join(map(str, plan)), spent),
+            "seconds_per_pair": sec}
 
 
 def serve_bench(args, torch, L, srv16, kgc16, plan16):
@@ -216,6 +227,10 @@ def main():
         plans = [[1] * levels, [2] * (levels // 2) + [1] * (levels % 2), [3] * (levels // 3) + [1] * (levels % 3)]
     plan = plans[0]
     torch.cuda.set_device(0)
+    # All library work of the bench runs on one non-default stream (HIP graph
+    # capture needs one; the library keeps its workspaces per stream).
+    s_main = torch.cuda.Stream()
+    torch.cuda.set_stream(s_main)
     n, ln, N = w.n_clients, w.n_ct, w.N
     P = w.n_pairs
     scale = 2.0 ** w.scale_log2
@@ -295,13 +310,46 @@ def main():
         srv.masked_sum(cts, masks, out=agg)
         kgc.decrypt(dist, out=dec)
 
-    for _ in range(args.warmup):
+    # With --graph (default) the step is captured once into a HIP graph and
+    # replayed: after the warmup has grown the stream's workspaces the library
+    # allocates, copies and synchronizes nothing inside it, and issues no memset.
+    graph = None
+    for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
+    eager = [t.clone() for t in (dist, sumdis, agg, dec)]
+    if args.graph:
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s_main):
+                step()
+            torch.cuda.synchronize()
+            graph_ok = True
+            for rep in range(3):
+                # eager work and a synchronization between replays, then every
+                # replay is compared with the eager result
+                if rep == 1:
+                    step()
+                for t in (dist, sumdis, agg, dec):
+                    t.fill_(-1)
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                graph_ok &= all(bool(torch.equal(a, b)) for a, b in zip((dist, sumdis, agg, dec), eager))
+            if graph_ok:
+                graph = g
+            log(f"[bench] HIP graph capture {'verified on 3 replays' if graph_ok else 'MISMATCH: timing eager'}")
+        except Exception as e:  # capture is optional; the eager path is the same work
+            log(f"[bench] HIP graph capture unavailable ({e}); timing eager launches")
+    del eager
     log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / max(1, args.steps)
@@ -355,10 +403,11 @@ def main():
         log(f"[bench] per-op form: {tp / len(pairs) * 1e3:.1f} ms/pair -> {len(pairs) / tp:.2f} distances/s")
 
     # ---- roofline of the dominant kernel ------------------------------------------
-    # Candidates: the fused pair-triple kernel (one launch per step, integer-ALU
-    # bound: 10 32x32->64 multiply-adds per update in the 25-bit split form) and
-    # the NTT passes of the key switches (HBM bound).  The one with the larger
-    # share of the step is reported.
+    # Candidates: the fused pair-triple kernel (one launch per step, FP64-ALU
+    # bound: 23 FP64 lane-instructions per update in the Barrett form -- two
+    # subtractions, three products of six instructions, three accumulations)
+    # and the NTT passes of the key switches (HBM bound).  The one with the
+    # larger share of the step is reported.
     roof = None
     if args.stages:
         nt = ntt_roofline(torch, srv, 64 if w.log_n >= 15 else 256)
@@ -366,9 +415,9 @@ def main():
         limb_ntts_per_ks = nq + srv.dnum * nq + 2 * srv.np + 2 * nq  # (L+1+K-alpha) = L+1 as alpha = K
         ntt_ms_step = ks_count * limb_ntts_per_ks * nt["transform_ms_per_limb_poly"]
         updates = P * ln * nq * N
-        a2 = {"bound": "alu", "achieved": 10 * updates / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e12,
-              "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "traffic": None, "kernel": "pair_triples_kernel",
-              "units_per_launch": "%d updates x 10 mad-ops" % updates,
+        a2 = {"bound": "alu", "achieved": A2_OPS_PER_UPDATE * updates / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e12,
+              "peak": VALU_PEAK_TOPS, "unit": "T FP64 lane-ops/s", "traffic": None, "kernel": "pair_triples_kernel",
+              "units_per_launch": "%d updates x %d FP64 lane-ops" % (updates, A2_OPS_PER_UPDATE),
               "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
         ntt = {"bound": "hbm", "achieved": nt["bytes_per_launch"] / (nt["launch_ms"] / 1e3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "kernel": "ntt_fast_kernel",
@@ -378,7 +427,7 @@ def main():
             r["frac"] = r["achieved"] / r["peak"]
         roof = ntt if ntt_ms_step > a2["est_ms_per_step"] else a2
         extra["kernels"] = {"pair_triples": a2, "ntt": ntt}
-        log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} TOP/s, {a2['frac']:.1%} of VALU); "
+        log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} T FP64 ops/s, {a2['frac']:.1%} of VALU); "
             f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step")
 
     if args.serve:
@@ -412,6 +461,7 @@ def main():
                    "clients": n, "dim": w.dim, "ciphertexts_per_client": ln, "pairs": P, "plan": plan,
                    "scale_log2": w.scale_log2},
         "check": check,
+        "hip_graph": graph is not None,
         "ingest_s": {"encode_host": t_enc_host, "encrypt_device": t_enc_dev, "keygen": t_keys},
         "roofline": roof,
         "cpu_baseline": base,

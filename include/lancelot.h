@@ -217,7 +217,7 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
 
 /* Launch-shape tuning, results unchanged (every shape computes the same
  * residues): "pair_lanes" (8/16/32/64 coefficients per workgroup of the pair
- * kernel), "pair_ppt" (1/3/6 pairs per lane), "ks_chunk" (1..256
+ * kernel), "pair_ppt" (1/3/4/6 pairs per lane), "ks_chunk" (1..256
  * ciphertexts per key-switch batch).  LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

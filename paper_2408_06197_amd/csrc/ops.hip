@@ -163,21 +163,33 @@ int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, 
 
 // ---- fused subtract / square / lazy accumulate over all pairs --------------
 //
-// Workgroup = (tile of T coefficients, limb l, chunk of pairs).  KB packed
+// Workgroup = (tile of T coefficients, limb l, chunk of pairs).  PT_KB packed
 // ciphertexts at a time, the tiles of all n clients (both components) are
 // staged in LDS once -- as exact doubles -- and every pair of the chunk reads
 // them from there.  A lane owns one coefficient of PPT pairs and keeps their
 // triple accumulators in registers across all k.  T and PPT are tuning
 // parameters (lc_set_tuning); the defaults come from measurements on MI355X.
 //
+// LDS layout is [client * 2 + comp][PT_KB][T], so with T and PT_KB known at
+// compile time a lane reads all of its operands at one base address per
+// client plus immediate offsets.  Ciphertexts past len are staged as zeros
+// and pair slots past P compute on clients (0, 1) and are not stored, so the
+// inner loop carries no branches and the compiler can issue every LDS read of
+// a k-step before the arithmetic that waits on them.  (Issuing a batch's
+// staging loads together, or double buffering the tile through registers,
+// measured no faster on MI355X: the staging is hidden by the second
+// workgroup on each CU.)
+//
 // Arithmetic is the FP64 Barrett form of modarith.h: differences x = a - b
-// lie in (-q, q); each product comes back as an integer r with |r| <= 0.875 q;
-// the accumulators (|acc| <= q/2 + 1 after a reduction) take at most
-// KB * 1.75 q <= 7 q before the next reduction, so they stay below 2^53 and
-// every value is exact.  The canonical residue is taken once at the end.
+// lie in (-q, q), so |x y / q| < q < 2^50 and the quotient estimate is off by
+// less than 1, giving each product as an integer r with |r| < q.  The
+// accumulators (|acc| <= q/2 + 1 after a reduction) take PT_KB = 4 such
+// products before the next reduction (the cross term is accumulated once and
+// doubled at the end), so they stay below 4.5 q < 2^53 and every value is exact.  The
+// canonical residue is taken once at the end.
 
 constexpr int PT_MAXN = 64;     // clients per call
-constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier (at most)
+constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
 constexpr size_t PT_LDS = 64 * 1024;
 
 __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
@@ -193,13 +205,13 @@ __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
 
 __host__ __device__ inline int pair_index(int n, int i, int j) { return i * (2 * n - i - 1) / 2 + (j - i - 1); }
 
-template <int PPT>
+template <int T, int PPT>
 __global__ void __launch_bounds__(1024)
 pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int P, u64 *d01, u64 d01_stride,
-                    u64 *d2, u64 d2_stride, int KB, int accumulate)
+                    u64 *d2, u64 d2_stride, int accumulate)
 {
-    extern __shared__ double tile[];  // [KB][n][2][T]
-    const int T = blockDim.x;         // coefficient lanes
+    extern __shared__ double tile[];  // [n * 2][PT_KB][T]
+    constexpr int ROW = PT_KB * T;    // doubles per (client, comp)
     const int G = blockDim.y;         // pair groups
     const int lane = threadIdx.x, g = threadIdx.y;
     const int tid = g * T + lane;
@@ -208,46 +220,43 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
     const u64 N = dp.N;
     const u64 S = (u64)dp.nq * N;
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
-    const int per_k = n * 2 * T;
+    const int staged = n * 2 * ROW;
 
-    // pair r of this lane is p = pbase + r G; its two clients' LDS offsets
-    // are packed into one register
+    // pair r of this lane is p = pbase + r G; its two clients' tile offsets
     const int pbase = blockIdx.z * (G * PPT) + g;
-    int offs[PPT];
+    int oa[PPT], ob[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
         int p = pbase + r * G, i = 0, j = 1;
         if (p < P) pair_of_index(p, n, i, j);
-        offs[r] = ((i * 2) * T + lane) | (((j * 2) * T + lane) << 16);
+        oa[r] = i * 2 * ROW + lane;
+        ob[r] = j * 2 * ROW + lane;
     }
     double acc[PPT][3];
 #pragma unroll
     for (int r = 0; r < PPT; r++) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
 
+    // Staged element e is (client * 2 + comp, kk, t) = (e / ROW, e / T % PT_KB, e % T).
     const u64 client_stride = (u64)len * 2 * S;
     const u64 off = (u64)l * N + (u64)blockIdx.x * T;
-    for (int k0 = 0; k0 < len; k0 += KB) {
-        const int kb = min(KB, len - k0);
-        for (int idx = tid; idx < kb * per_k; idx += nthreads) {
-            int row = idx / T, t = idx - row * T;
-            int kk = row / (2 * n), rr = row - kk * 2 * n;  // rr = client * 2 + comp
-            tile[idx] = u64_to_d(cts[(u64)(rr >> 1) * client_stride + (u64)(k0 + kk) * 2 * S + (u64)(rr & 1) * S +
-                                     off + t]);
+    for (int k0 = 0; k0 < len; k0 += PT_KB) {
+        for (int e = tid; e < staged; e += nthreads) {
+            const int t = e % T, kk = (e / T) % PT_KB, rr = e / ROW;
+            double v = 0.0;
+            if (k0 + kk < len)
+                v = u64_to_d(cts[(u64)(rr >> 1) * client_stride + (u64)(k0 + kk) * 2 * S + (u64)(rr & 1) * S + off + t]);
+            tile[e] = v;
         }
         __syncthreads();
-        for (int kk = 0; kk < kb; kk++) {
-            const double *tl = tile + kk * per_k;
+#pragma unroll
+        for (int kk = 0; kk < PT_KB; kk++) {
 #pragma unroll
             for (int r = 0; r < PPT; r++) {
-                if (pbase + r * G < P) {
-                    const int oa = offs[r] & 0xffff, ob = offs[r] >> 16;
-                    double x0 = tl[oa] - tl[ob];
-                    double x1 = tl[oa + T] - tl[ob + T];
-                    double m = mulmod_d(x0, x1, q, qinv);
-                    acc[r][0] += mulmod_d(x0, x0, q, qinv);
-                    acc[r][1] += m + m;
-                    acc[r][2] += mulmod_d(x1, x1, q, qinv);
-                }
+                double x0 = tile[oa[r] + kk * T] - tile[ob[r] + kk * T];
+                double x1 = tile[oa[r] + ROW + kk * T] - tile[ob[r] + ROW + kk * T];
+                acc[r][0] += mulmod_d(x0, x0, q, qinv);
+                acc[r][1] += mulmod_d(x0, x1, q, qinv);
+                acc[r][2] += mulmod_d(x1, x1, q, qinv);
             }
         }
 #pragma unroll
@@ -264,15 +273,32 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
         const u64 p = (u64)(pbase + r * G);
         if (p < (u64)P) {
             u64 *o0 = d01 + p * d01_stride + o, *o1 = o0 + S, *o2 = d2 + p * d2_stride + o;
-            if (accumulate) {  // |acc| <= q/2 + 1, previous value in [0, q): the sum stays within 2q
+            double c1 = acc[r][1] + acc[r][1];  // |2 acc| <= q + 2
+            if (accumulate) {  // previous values in [0, q): the sums stay below 2q + 2
                 acc[r][0] += u64_to_d(*o0);
-                acc[r][1] += u64_to_d(*o1);
+                c1 += u64_to_d(*o1);
                 acc[r][2] += u64_to_d(*o2);
             }
             *o0 = d_to_canonical(acc[r][0], q, qinv);
-            *o1 = d_to_canonical(acc[r][1], q, qinv);
+            *o1 = d_to_canonical(c1, q, qinv);
             *o2 = d_to_canonical(acc[r][2], q, qinv);
         }
+    }
+}
+
+template <int T>
+static void launch_pt(int ppt, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &dp, const u64 *cts,
+                      int n, int len, int P, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride, int accumulate)
+{
+    switch (ppt) {
+    case 1: hipLaunchKernelGGL((pair_triples_kernel<T, 1>), grid, block, lds, s, dp, cts, n, len, P, d01, d01_stride,
+                               d2, d2_stride, accumulate); break;
+    case 3: hipLaunchKernelGGL((pair_triples_kernel<T, 3>), grid, block, lds, s, dp, cts, n, len, P, d01, d01_stride,
+                               d2, d2_stride, accumulate); break;
+    case 4: hipLaunchKernelGGL((pair_triples_kernel<T, 4>), grid, block, lds, s, dp, cts, n, len, P, d01, d01_stride,
+                               d2, d2_stride, accumulate); break;
+    default: hipLaunchKernelGGL((pair_triples_kernel<T, 6>), grid, block, lds, s, dp, cts, n, len, P, d01,
+                                d01_stride, d2, d2_stride, accumulate); break;
     }
 }
 
@@ -282,22 +308,21 @@ int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d0
     if (n < 2 || n > PT_MAXN) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
     if (len < 1) return fail(c, LC_EINVAL, "len must be >= 1");
     int P = n * (n - 1) / 2;
-    int ppt = c->tune.pair_ppt, T = c->tune.pair_lanes;
+    int ppt = c->tune.pair_ppt;
     if (P <= 64) ppt = 1;  // few pairs: one per lane
-    T = (int)std::min<u64>((u64)T, c->N);
+    // coefficient lanes: the tuned value, at most N, and small enough that the
+    // staged tiles of all n clients fit the LDS budget
+    int T = c->tune.pair_lanes;
+    while (T > 8 && ((u64)T > c->N || (size_t)n * 2 * PT_KB * T * sizeof(double) > PT_LDS)) T >>= 1;
     int G = std::max(1, std::min((P + ppt - 1) / ppt, 1024 / T));
     int chunks = (P + G * ppt - 1) / (G * ppt);
     dim3 grid((u32)(c->N / T), (u32)c->nq, (u32)chunks), block(T, G);
-    size_t per_k = (size_t)n * 2 * T * sizeof(double);
-    int kb = (int)std::max<size_t>(1, std::min<size_t>(PT_KB, PT_LDS / per_k));
-    size_t lds = (size_t)kb * per_k;
-    switch (ppt) {
-    case 1: hipLaunchKernelGGL((pair_triples_kernel<1>), grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride,
-                               d2, d2_stride, kb, accumulate); break;
-    case 3: hipLaunchKernelGGL((pair_triples_kernel<3>), grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride,
-                               d2, d2_stride, kb, accumulate); break;
-    default: hipLaunchKernelGGL((pair_triples_kernel<6>), grid, block, lds, s, c->dp, cts, n, len, P, d01,
-                                d01_stride, d2, d2_stride, kb, accumulate); break;
+    size_t lds = (size_t)n * 2 * PT_KB * T * sizeof(double);
+    switch (T) {
+    case 8: launch_pt<8>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
+    case 16: launch_pt<16>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
+    case 32: launch_pt<32>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
+    default: launch_pt<64>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
     }
     LC_HIP(c, hipGetLastError());
     return LC_OK;
