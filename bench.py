@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
     p.add_argument("--no-graph", dest="graph", action="store_false", default=True,
                    help="time eager launches instead of a captured HIP graph")
+    p.add_argument("--no-ntt-micro", dest="ntt_micro", action="store_false", default=True,
+                   help="skip the mixed-degree NTT / hoisted key-switch micro-workload")
     p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
                    help="also run the serving form: ROUNDS Poisson-arriving aggregation rounds")
     p.add_argument("--serve-slots", type=int, default=4)
@@ -92,6 +94,109 @@ def ntt_roofline(torch, srv, batch):
     del x
     return {"launch_ms": per_launch_ms, "bytes_per_launch": bytes_per_launch, "limb_polys": npoly,
             "transform_ms_per_limb_poly": ms / npoly}
+
+
+# ---- mixed-degree NTT and hoisted key-switch micro-workload --------------------
+# 4096 single-limb polynomials of mixed ring degree in ratio 4:2:1, on one
+# chain of 50-bit primes = 1 mod 2^17 (NTT-friendly for every degree): poly i
+# of a degree uses limb prime i mod (L+1) of that degree's chain.  The key
+# switch groups consecutive polynomials of a degree into RNS c1's with
+# (L+1, K = alpha) = (3,1) / (6,2) / (24,8), so dnum = 3 for all three.
+D4 = ((12, 2341, 3, 1), (14, 1170, 6, 2), (16, 585, 24, 8))  # (log N, polys, L+1, K)
+
+
+def d4_contexts(L):
+    return [L.Context(ln, (50,) * nq, (50,) * k, log_m=17, device=0, role=L.ROLE_KGC) for ln, _, nq, k in D4]
+
+
+def d4_polys(torch, ctxs, seed):
+    """Per degree: (full groups [g][L+1][N], ragged tail [1][r][N] or None),
+    coefficients uniform in [0, q) of each poly's prime."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    out = []
+    for ctx, (_, cnt, nq, _) in zip(ctxs, D4):
+        full, rem = divmod(cnt, nq)
+        x = torch.empty((full, nq, ctx.N), dtype=torch.int64, device="cuda")
+        for l in range(nq):
+            x[:, l].random_(0, int(ctx.moduli[l]), generator=gen)
+        y = None
+        if rem:
+            y = torch.empty((1, rem, ctx.N), dtype=torch.int64, device="cuda")
+            for l in range(rem):
+                y[:, l].random_(0, int(ctx.moduli[l]), generator=gen)
+        out.append((x, y))
+    return out
+
+
+def d4_ntt(ctxs, polys, inverse=False):
+    for ctx, (x, y) in zip(ctxs, polys):
+        f = ctx.ntt_inv if inverse else ctx.ntt_fwd
+        f(x, nlimb=x.shape[1])
+        if y is not None:
+            f(y, nlimb=y.shape[1])
+
+
+def d4_rotation_steps(log_n):
+    return [1 << j for j in range(log_n - 1)]
+
+
+def ntt_micro(torch, L):
+    """Forward + inverse NTT of the 4096 mixed-degree polys (checked to round
+    trip), then one hoisted key switch per c1 over log2(N/2) power-of-two
+    rotations.  Algorithmic NTT traffic: one read + one write of every poly
+    per direction (16 N bytes per poly)."""
+    ctxs = d4_contexts(L)
+    polys = d4_polys(torch, ctxs, 4004)
+    keep = [(x.clone(), None if y is None else y.clone()) for x, y in polys]
+    alg_bytes = sum(cnt * (1 << ln) * 16 for ln, cnt, _, _ in D4)
+    res = {"polys": {str(1 << ln): cnt for ln, cnt, _, _ in D4}, "algorithmic_bytes_per_direction": alg_bytes}
+    best = None
+    for sub in (0, 32768, 65536):
+        for c in ctxs:
+            c.set_tuning("ntt_sub_kb", sub)
+        fwd = event_time(torch, lambda: d4_ntt(ctxs, polys), reps=3)
+        inv = event_time(torch, lambda: d4_ntt(ctxs, polys, inverse=True), reps=3)
+        res.setdefault("fwd_ms_by_ntt_sub_kb", {})[str(sub)] = fwd
+        res.setdefault("inv_ms_by_ntt_sub_kb", {})[str(sub)] = inv
+        if best is None or fwd + inv < best[0] + best[1]:
+            best = (fwd, inv, sub)
+    for c in ctxs:
+        c.set_tuning("ntt_sub_kb", best[2])
+    torch.cuda.synchronize()
+    # the timed transforms ran in forward/inverse pairs: the data is back
+    res["round_trip_exact"] = all(bool(torch.equal(x, a)) and (y is None or bool(torch.equal(y, b)))
+                                  for (x, y), (a, b) in zip(polys, keep))
+    fwd, inv = best[0], best[1]
+    res.update({"ntt_sub_kb": best[2], "fwd_ms": fwd, "inv_ms": inv,
+                "fwd_GBps": alg_bytes / (fwd / 1e3) / 1e9, "inv_GBps": alg_bytes / (inv / 1e3) / 1e9})
+    log(f"[bench] NTT micro (2341x2^12 + 1170x2^14 + 585x2^16): fwd {fwd:.2f} ms ({res['fwd_GBps']:.0f} GB/s), "
+        f"inv {inv:.2f} ms ({res['inv_GBps']:.0f} GB/s), sub-batch {best[2]} KiB, round trip "
+        f"{'exact' if res['round_trip_exact'] else 'MISMATCH'}")
+    del keep
+    ks = {}
+    for ctx, (x, _), (ln, cnt, nq, k) in zip(ctxs, polys, D4):
+        steps = d4_rotation_steps(ln)
+        ctx.keygen(4104)
+        ctx.keygen_rotation(4104, steps)
+        g = x.shape[0]
+        ct = torch.empty((g, 2, nq, ctx.N), dtype=torch.int64, device="cuda")
+        ct[:, 1].copy_(x)
+        ct[:, 0].copy_(x.flip(0))
+        out = torch.empty((g, len(steps), 2, nq, ctx.N), dtype=torch.int64, device="cuda")
+        ms = event_time(torch, lambda: ctx.rotate_hoisted(ct, steps, out=out), reps=2)
+        key_bytes = ctx.dnum * 2 * (nq + k) * ctx.N * 8
+        # algorithmic: read c1 once and c0 per step, keys once per call, write every output
+        alg = g * (nq * ctx.N * 8 * (1 + len(steps)) + len(steps) * 2 * nq * ctx.N * 8) + len(steps) * key_bytes
+        ks[str(1 << ln)] = {"c1": g, "limbs": nq, "special": k, "dnum": ctx.dnum, "rotations": len(steps),
+                            "ms": ms, "rotations_per_s": g * len(steps) / (ms / 1e3),
+                            "algorithmic_GBps": alg / (ms / 1e3) / 1e9}
+        log(f"[bench] hoisted KS 2^{ln}: {g} c1 x {len(steps)} rotations in {ms:.1f} ms "
+            f"({ks[str(1 << ln)]['algorithmic_GBps']:.0f} GB/s algorithmic)")
+        del ct, out
+    res["hoisted_keyswitch"] = ks
+    del polys
+    return res
 
 
 def cpu_baseline(w, plan, n_cts, min_seconds=12.0):
@@ -303,6 +408,18 @@ def main():
                     bestp = (ms, pl)
             plan = bestp[1]
         tuned["plan"] = plan
+        # key-switch inner-product width and batch, on the chosen plan (the NTT
+        # sub-batch knob measured no gain at this size and stays off)
+        for name, values in (("mac_cts", (8, 16)), ("ks_chunk", (32, 64, 128))):
+            bestv = None
+            for v in values:
+                srv.set_tuning(name, v)
+                ms = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=plan, out=dist))
+                tuned.setdefault(name + "_ms", {})[str(v)] = ms
+                if bestv is None or ms < bestv[0]:
+                    bestv = (ms, v)
+            srv.set_tuning(name, bestv[1])
+            tuned[name] = bestv[1]
         log(f"[bench] autotuned: {tuned}")
 
     def step():
@@ -430,9 +547,16 @@ def main():
         log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} T FP64 ops/s, {a2['frac']:.1%} of VALU); "
             f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step")
 
-    if args.serve:
-        del cts
+    # the round's ciphertexts are no longer needed
+    used_graph = graph is not None
+    del cts, dist, sumdis, agg, dec, masks, graph
+    torch.cuda.empty_cache()
+
+    if args.ntt_micro:
+        extra["ntt_micro"] = ntt_micro(torch, L)
         torch.cuda.empty_cache()
+
+    if args.serve:
         if w.log_n != 16:
             log("[bench] --serve needs the N=2^16 workload's contexts; skipped")
         else:
@@ -461,7 +585,7 @@ def main():
                    "clients": n, "dim": w.dim, "ciphertexts_per_client": ln, "pairs": P, "plan": plan,
                    "scale_log2": w.scale_log2},
         "check": check,
-        "hip_graph": graph is not None,
+        "hip_graph": used_graph,
         "ingest_s": {"encode_host": t_enc_host, "encrypt_device": t_enc_dev, "keygen": t_keys},
         "roofline": roof,
         "cpu_baseline": base,

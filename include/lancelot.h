@@ -218,7 +218,10 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
 /* Launch-shape tuning, results unchanged (every shape computes the same
  * residues): "pair_lanes" (8/16/32/64 coefficients per workgroup of the pair
  * kernel), "pair_ppt" (1/3/4/6 pairs per lane), "ks_chunk" (1..256
- * ciphertexts per key-switch batch).  LC_EINVAL for unknown names/values. */
+ * ciphertexts per key-switch batch), "ntt_sub_kb" (0..4194304: two-pass NTTs
+ * run both passes per sub-batch of about this many KiB; 0 = whole batch),
+ * "mac_cts" (8/16 ciphertexts per lane of the key-switch inner product).
+ * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 
 #ifdef __cplusplus

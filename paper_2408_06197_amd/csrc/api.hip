@@ -687,6 +687,12 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "ks_chunk") {
         if (value < 1 || value > 256) return fail(c, LC_EINVAL, "ks_chunk: 1..256");
         c->tune.ks_chunk = value;
+    } else if (k == "mac_cts") {
+        if (value != 8 && value != 16) return fail(c, LC_EINVAL, "mac_cts: 8/16");
+        c->tune.mac_cts = value;
+    } else if (k == "ntt_sub_kb") {
+        if (value < 0 || value > (1 << 22)) return fail(c, LC_EINVAL, "ntt_sub_kb: 0..4194304");
+        c->tune.ntt_sub_kb = value;
     } else {
         return fail(c, LC_EINVAL, "unknown tuning parameter " + k);
     }

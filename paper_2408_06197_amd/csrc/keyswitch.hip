@@ -32,30 +32,34 @@ strided_copy_kernel(const u64 *src, u64 sstride, u64 *dst, u64 dstride, u64 word
 }
 
 // raised[b][d][l][j] for l outside digit d, coefficient domain.
+//
+// FP64 Barrett form: y_a = [x^_a (Q_d/q_a)^-1]_{q_a} is taken to its
+// canonical representative (the conversion is defined on it), then each
+// product y_a (Q_d/q_a mod m_l) < q_a m_l comes back with |r| <= 0.875 m_l;
+// at most MAX_NP of them are summed before the canonical read-out.
 __global__ void __launch_bounds__(KS_THREADS)
-modup_bconv_kernel(DevParams dp, const u64 *xhat, u64 *raised, u64 count)
+modup_bconv_kernel(DevParams dp, const u64 *xhat, u64 *raised)
 {
-    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over count * dnum * N
-    if (e >= count * dp.dnum * (u64)dp.N) return;
-    u64 j = e & (dp.N - 1);
-    u64 bd = e >> dp.log_n;
-    int d = (int)(bd % dp.dnum);
-    u64 b = bd / dp.dnum;
-    int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
-    u64 y[MAX_NP];
+    // grid (N / blockDim.x, count * dnum): the digit and ciphertext are
+    // uniform over the workgroup, so the conversion constants are scalar loads
+    const u64 j = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const int d = (int)(blockIdx.y % (u32)dp.dnum);
+    const u64 b = blockIdx.y / (u32)dp.dnum;
+    const int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
+    double y[MAX_NP];
     for (int a = 0; a < na; a++) {
         const ModConst &mc = dp.mc[a0 + a];
-        u64 v = xhat[(b * dp.nq + a0 + a) * dp.N + j];
-        y[a] = mul_shoup(v, dp.up_inv[d * dp.alpha + a], dp.up_inv_sh[d * dp.alpha + a], mc.m);
+        double v = u64_to_d(xhat[(b * dp.nq + a0 + a) * dp.N + j]);
+        y[a] = canon_d(mulmod_d(v, dp.up_inv_d[d * dp.alpha + a], mc.qd, mc.qinv), mc.qd, mc.qinv);
     }
     u64 *out = raised + (b * dp.dnum + d) * (u64)dp.ne * dp.N + j;
+    const double *fac = dp.up_fac_d + (u64)d * dp.alpha * dp.ne;
     for (int l = 0; l < dp.ne; l++) {
         if (l >= a0 && l < a0 + na) continue;
-        Split3 s;
-        split_zero(s);
-        const u64 *fac = dp.up_fac + (u64)d * dp.alpha * dp.ne + l;
-        for (int a = 0; a < na; a++) split_mac(s, y[a], fac[(u64)a * dp.ne]);
-        out[(u64)l * dp.N] = reduce_split(s, dp.mc[l]);
+        const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+        double s = 0.0;
+        for (int a = 0; a < na; a++) s += mulmod_d(y[a], fac[(u64)a * dp.ne + l], q, qinv);
+        out[(u64)l * dp.N] = d_to_canonical(s, q, qinv);
     }
 }
 
@@ -69,11 +73,11 @@ struct KeySet {
 //
 // A lane owns one coefficient (l, j) of MAC_B ciphertexts: each key value is
 // read once and used for all MAC_B of them (the key of a block is read once per
-// MAC_B ciphertexts instead of once per ciphertext).  Products use the FP64
-// Barrett form (|x key| reduced to at most 0.875 q); the two accumulators per
-// ciphertext are reduced after every 8 products, so they stay below 8 q.
-constexpr int MAC_B = 8;
-
+// MAC_B ciphertexts instead of once per ciphertext; MAC_B = 8 or 16 is a
+// tuning choice).  Products use the FP64 Barrett form (|x key| reduced to at
+// most 0.8125 q); the two accumulators per ciphertext are reduced after every
+// 8 products, so they stay below 7 q.
+template <int MAC_B>
 __global__ void __launch_bounds__(KS_THREADS)
 mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, u64 *acc, u64 count)
 {
@@ -127,7 +131,8 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
     }
 }
 
-// v[b][k][l][j] = BConv_{P->Q} of the (coefficient-domain) P limbs of acc.
+// v[b][k][l][j] = BConv_{P->Q} of the (coefficient-domain) P limbs of acc,
+// in the same FP64 form as the ModUp conversion.
 __global__ void __launch_bounds__(KS_THREADS)
 moddown_bconv_kernel(DevParams dp, const u64 *acc, u64 *v, u64 count)
 {
@@ -135,17 +140,18 @@ moddown_bconv_kernel(DevParams dp, const u64 *acc, u64 *v, u64 count)
     if (e >= count * 2 * (u64)dp.N) return;
     u64 j = e & (dp.N - 1), bk = e >> dp.log_n;
     const u64 *A = acc + bk * (u64)dp.ne * dp.N;
-    u64 y[MAX_NP];
+    double y[MAX_NP];
     for (int k = 0; k < dp.np; k++) {
         const ModConst &mc = dp.mc[dp.nq + k];
-        y[k] = mul_shoup(A[(u64)(dp.nq + k) * dp.N + j], dp.dn_inv[k], dp.dn_inv_sh[k], mc.m);
+        double a = u64_to_d(A[(u64)(dp.nq + k) * dp.N + j]);
+        y[k] = canon_d(mulmod_d(a, dp.dn_inv_d[k], mc.qd, mc.qinv), mc.qd, mc.qinv);
     }
     u64 *out = v + bk * (u64)dp.nq * dp.N + j;
     for (int l = 0; l < dp.nq; l++) {
-        Split3 s;
-        split_zero(s);
-        for (int k = 0; k < dp.np; k++) split_mac(s, y[k], dp.dn_fac[(u64)k * dp.nq + l]);
-        out[(u64)l * dp.N] = reduce_split(s, dp.mc[l]);
+        const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+        double s = 0.0;
+        for (int k = 0; k < dp.np; k++) s += mulmod_d(y[k], dp.dn_fac_d[(u64)k * dp.nq + l], q, qinv);
+        out[(u64)l * dp.N] = d_to_canonical(s, q, qinv);
     }
 }
 
@@ -208,8 +214,9 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                            xhat, words, words, B);
         LC_HIP(c, hipGetLastError());
         if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
-        hipLaunchKernelGGL(modup_bconv_kernel, dim3(blocks_for(B * dnum * N)), dim3(KS_THREADS), 0, s, c->dp, xhat,
-                           raised, B);
+        const u32 tpb = (u32)std::min<u64>(N, KS_THREADS);
+        hipLaunchKernelGGL(modup_bconv_kernel, dim3((u32)(N / tpb), (u32)(B * dnum)), dim3(tpb), 0, s, c->dp, xhat,
+                           raised);
         LC_HIP(c, hipGetLastError());
         if ((rc = launch_ntt_fwd(c, PolyBatch{raised, B * dnum, ne, (u64)ne, 0, 1}, s))) return rc;
         for (int g = 0; g < ngroups; g++) {
@@ -220,8 +227,12 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                 ks.key[t] = G.keys[t];
                 ks.perm[t] = G.perms[t];
             }
-            hipLaunchKernelGGL(mac_kernel, dim3(blocks_for((u64)ne * N), (u32)((B + MAC_B - 1) / MAC_B)),
-                               dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
+            if (c->tune.mac_cts == 16)
+                hipLaunchKernelGGL((mac_kernel<16>), dim3(blocks_for((u64)ne * N), (u32)((B + 15) / 16)),
+                                   dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
+            else
+                hipLaunchKernelGGL((mac_kernel<8>), dim3(blocks_for((u64)ne * N), (u32)((B + 7) / 8)),
+                                   dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
             LC_HIP(c, hipGetLastError());
             if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
             hipLaunchKernelGGL(moddown_bconv_kernel, dim3(blocks_for(B * 2 * N)), dim3(KS_THREADS), 0, s, c->dp, acc,

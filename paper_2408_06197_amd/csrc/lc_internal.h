@@ -31,6 +31,7 @@ struct DevParams {
     const u64 *up_fac;              // [dnum][alpha][ne]: (Q_d / q_a) mod m_l
     const u64 *dn_inv, *dn_inv_sh;  // [np]: (P / p_k)^-1 mod p_k
     const u64 *dn_fac;              // [np][nq]: (P / p_k) mod q_l
+    const double *up_inv_d, *up_fac_d, *dn_inv_d, *dn_fac_d;  // the four tables above as doubles
     const u64 *pinv, *pinv_sh;      // [nq]: P^-1 mod q_l
     const u64 *pmod;                // [nq]: P mod q_l (gadget)
     const u64 *cdt;                 // [38]: Gaussian thresholds
@@ -78,9 +79,11 @@ struct Ctx {
 
     // launch-shape tuning (lc_set_tuning)
     struct Tuning {
-        int pair_lanes = 32;  // coefficients per workgroup of the pair-triple kernel
-        int pair_ppt = 6;     // pairs per lane (1, 3, 6 or 12)
+        int pair_lanes = 16;  // coefficients per workgroup of the pair-triple kernel
+        int pair_ppt = 6;     // pairs per lane (1, 3, 4 or 6)
         int ks_chunk = 64;    // ciphertexts per key-switch batch
+        int ntt_sub_kb = 0;   // two-pass NTTs run per sub-batch of this many KiB (0: whole batch)
+        int mac_cts = 8;      // ciphertexts per lane of the key-switch inner product (8 or 16)
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
 };

@@ -143,7 +143,17 @@ __device__ __forceinline__ double u64_to_d(u64 v)
     return __fma_rn((double)(u32)(v >> 32), 4294967296.0, (double)(u32)v);
 }
 
-// integer-valued double with |x| <= 2q to the canonical residue in [0, q).
+// integer-valued double with |x| < 2^52 to the canonical residue in [0, q),
+// still as a double.
+__device__ __forceinline__ double canon_d(double x, double q, double qinv)
+{
+    double r = reduce_d(x, q, qinv);   // |r| <= q/2 + 1
+    if (r < 0) r += q;
+    if (r >= q) r -= q;
+    return r;
+}
+
+// integer-valued double with |x| < 2^52 to the canonical residue in [0, q).
 __device__ __forceinline__ u64 d_to_canonical(double x, double q, double qinv)
 {
     double r = reduce_d(x, q, qinv);   // |r| <= q/2 + 1

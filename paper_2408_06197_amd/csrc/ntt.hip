@@ -304,6 +304,29 @@ static int plan_passes(int log_n, PassArgs *pass)
     return 2;
 }
 
+static int launch_fast(Ctx *c, const PolyBatch &b, const FastPass *fp, hipStream_t s, bool inverse)
+{
+    const u64 npoly = b.count * (u64)b.nlimb;
+    for (int k = 0; k < 2; k++) {
+        int i = inverse ? 1 - k : k;
+        const FastPass &P = fp[i];
+        int final_ = inverse ? (i == 0) : (i == 1);
+        u32 S = 1u << P.log_s;
+        u32 tiles = (u32)(c->N >> P.log_s) / (u32)P.cols;
+        dim3 grid((u32)npoly, tiles), block((u32)P.cols * (S / 16));
+        size_t lds = (size_t)P.cols * (S + S / 16) * sizeof(u64);
+        if (inverse) {
+            if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+            else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        } else {
+            if (P.blocks) launch_fast_one<false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+            else launch_fast_one<false, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        }
+        LC_HIP(c, hipGetLastError());
+    }
+    return LC_OK;
+}
+
 static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
 {
     u64 npoly = b.count * (u64)b.nlimb;
@@ -311,22 +334,22 @@ static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
     if (npoly > 0x7fffffffull) return fail(c, LC_EINVAL, "too many polynomials in one NTT batch");
     FastPass fp[2];
     if (plan_fast(c->log_n, fp)) {
-        for (int k = 0; k < 2; k++) {
-            int i = inverse ? 1 - k : k;
-            const FastPass &P = fp[i];
-            int final_ = inverse ? (i == 0) : (i == 1);
-            u32 S = 1u << P.log_s;
-            u32 tiles = (u32)(c->N >> P.log_s) / (u32)P.cols;
-            dim3 grid((u32)npoly, tiles), block((u32)P.cols * (S / 16));
-            size_t lds = (size_t)P.cols * (S + S / 16) * sizeof(u64);
-            if (inverse) {
-                if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
-                else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
-            } else {
-                if (P.blocks) launch_fast_one<false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
-                else launch_fast_one<false, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
-            }
-            LC_HIP(c, hipGetLastError());
+        // Both passes run over one sub-batch of about ntt_sub_kb KiB before the
+        // next, so that the first pass's output can still sit in the
+        // memory-side cache when the second pass reads it.  Sub-batches hold
+        // whole digit groups when own-digit limbs are skipped.
+        u64 gsub = b.count;
+        if (c->tune.ntt_sub_kb > 0) {
+            const u64 group_bytes = (u64)b.nlimb * c->N * sizeof(u64);
+            gsub = std::max<u64>(1, ((u64)c->tune.ntt_sub_kb << 10) / group_bytes);
+            if (b.skip_own_digit) gsub = std::max<u64>((u64)c->dnum, gsub / c->dnum * c->dnum);
+        }
+        for (u64 g0 = 0; g0 < b.count; g0 += gsub) {
+            PolyBatch sb = b;
+            sb.base = b.base + g0 * b.gstride * c->N;
+            sb.count = std::min(gsub, b.count - g0);
+            int rc = launch_fast(c, sb, fp, s, inverse);
+            if (rc) return rc;
         }
         return LC_OK;
     }

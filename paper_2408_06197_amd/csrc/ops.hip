@@ -110,53 +110,62 @@ int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, 
 }
 
 // out[k][comp][l][j] = sum_i cts[i][k][comp][l][j] * masks[i][l][j]
-// Two adjacent coefficients per lane (16-byte accesses), four clients' loads
-// in flight; FP64 Barrett products (|r| <= 0.875 q) summed with a reduction
-// after at most 8 clients.
-__global__ void __launch_bounds__(EW_THREADS)
-masked_sum_kernel(DevParams dp, const u64 *cts, int n, int len, const u64 *masks, u64 *out, u64 total2)
+//
+// Workgroup = (256 consecutive coefficients of one (limb, position) range,
+// MS_ROWS consecutive (k, comp) rows).  A lane owns one coefficient and the
+// MS_ROWS row accumulators; clients go in groups of 8 whose mask values are
+// loaded once into registers and used for every row, so the masks cost
+// 1 / MS_ROWS of a read per output instead of one (the client ciphertexts
+// are read exactly once).  FP64 Barrett products of residues below q come
+// back with |r| < q; a reduction follows every 4 products, so the
+// accumulators stay below 4.5 q < 2^53.
+constexpr int MS_TILE = 256;
+constexpr int MS_ROWS = 16;
+
+__global__ void __launch_bounds__(MS_TILE)
+masked_sum_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, const u64 *__restrict__ masks,
+                  u64 *__restrict__ out)
 {
-    u64 e2 = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over len * 2 * nq * N / 2
-    if (e2 >= total2) return;
-    u64 e = 2 * e2;
-    u64 S = (u64)dp.nq << dp.log_n;
-    u64 r = e % S;
-    int l = (int)(r >> dp.log_n);
+    const u64 S = (u64)dp.nq << dp.log_n;
+    const u64 r = (u64)blockIdx.x * MS_TILE + threadIdx.x;  // (limb, coefficient)
+    if (r >= S) return;
+    const int rows = 2 * len, row0 = blockIdx.y * MS_ROWS;
+    const int l = (int)(r >> dp.log_n);
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
-    u64 client_stride = (u64)len * 2 * S;
-    double a0 = 0.0, a1 = 0.0;
-    for (int i0 = 0; i0 < n; i0 += 4) {
-        ulonglong2 c2[4], m2[4];
+    const u64 client_stride = (u64)len * 2 * S;
+    double acc[MS_ROWS];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            int i = min(i0 + u, n - 1);
-            c2[u] = *reinterpret_cast<const ulonglong2 *>(cts + (u64)i * client_stride + e);
-            m2[u] = *reinterpret_cast<const ulonglong2 *>(masks + (u64)i * S + r);
-        }
+    for (int t = 0; t < MS_ROWS; t++) acc[t] = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 8) {
+        double m[8];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            if (i0 + u < n) {
-                a0 += mulmod_d(u64_to_d(c2[u].x), u64_to_d(m2[u].x), q, qinv);
-                a1 += mulmod_d(u64_to_d(c2[u].y), u64_to_d(m2[u].y), q, qinv);
+        for (int u = 0; u < 8; u++) m[u] = i0 + u < n ? u64_to_d(masks[(u64)(i0 + u) * S + r]) : 0.0;
+        const u64 *base = cts + (u64)i0 * client_stride + (u64)row0 * S + r;
+#pragma unroll
+        for (int t = 0; t < MS_ROWS; t++) {
+            if (row0 + t < rows) {
+                double c[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) c[u] = i0 + u < n ? u64_to_d(base[(u64)u * client_stride + (u64)t * S]) : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    acc[t] += mulmod_d(c[u], m[u], q, qinv);
+                    if (u == 3 || u == 7) acc[t] = reduce_d(acc[t], q, qinv);
+                }
             }
         }
-        if ((i0 & 7) == 4 || i0 + 4 >= n) {  // at most 8 products between reductions
-            a0 = reduce_d(a0, q, qinv);
-            a1 = reduce_d(a1, q, qinv);
-        }
     }
-    ulonglong2 o;
-    o.x = d_to_canonical(reduce_d(a0, q, qinv), q, qinv);
-    o.y = d_to_canonical(reduce_d(a1, q, qinv), q, qinv);
-    *reinterpret_cast<ulonglong2 *>(out + e) = o;
+#pragma unroll
+    for (int t = 0; t < MS_ROWS; t++)
+        if (row0 + t < rows) out[(u64)(row0 + t) * S + r] = d_to_canonical(acc[t], q, qinv);
 }
 
 int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s)
 {
-    u64 total2 = (u64)len * c->nq * c->N;  // pairs of coefficients (N is even)
-    if (!total2) return LC_OK;
-    hipLaunchKernelGGL(masked_sum_kernel, grid_for(total2, EW_THREADS), dim3(EW_THREADS), 0, s, c->dp, cts, n, len,
-                       masks, out, total2);
+    const u64 S = (u64)c->nq * c->N;
+    if (len < 1 || n < 1) return LC_OK;
+    dim3 grid((u32)((S + MS_TILE - 1) / MS_TILE), (u32)((2 * len + MS_ROWS - 1) / MS_ROWS));
+    hipLaunchKernelGGL(masked_sum_kernel, grid, dim3(MS_TILE), 0, s, c->dp, cts, n, len, masks, out);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }

@@ -251,6 +251,8 @@ int build_params(Ctx *c, const lc_params *prm)
     d.up_inv = upload(c, upi);
     d.up_inv_sh = upload(c, upis);
     d.up_fac = upload(c, upf);
+    d.up_inv_d = upload(c, std::vector<double>(upi.begin(), upi.end()));
+    d.up_fac_d = upload(c, std::vector<double>(upf.begin(), upf.end()));
 
     // ModDown constants
     std::vector<u64> dni(np), dnis(np), dnf((size_t)np * nq), pinv(nq), pinvs(nq), pmod(nq);
@@ -277,6 +279,8 @@ int build_params(Ctx *c, const lc_params *prm)
     d.dn_inv = upload(c, dni);
     d.dn_inv_sh = upload(c, dnis);
     d.dn_fac = upload(c, dnf);
+    d.dn_inv_d = upload(c, std::vector<double>(dni.begin(), dni.end()));
+    d.dn_fac_d = upload(c, std::vector<double>(dnf.begin(), dnf.end()));
     d.pinv = upload(c, pinv);
     d.pinv_sh = upload(c, pinvs);
     d.pmod = upload(c, pmod);
@@ -287,7 +291,8 @@ int build_params(Ctx *c, const lc_params *prm)
     c->cdt_host = cdt;
 
     if (c->device < 0) return LC_OK;
-    if (!d.twd || !d.itwd) return fail(c, LC_ENOMEM, "could not upload parameter tables");
+    if (!d.twd || !d.itwd || !d.up_inv_d || !d.up_fac_d || !d.dn_inv_d || !d.dn_fac_d)
+        return fail(c, LC_ENOMEM, "could not upload parameter tables");
     if (!d.mc || !d.tw || !d.tw_sh || !d.itw || !d.itw_sh || !d.ninv || !d.ninv_sh || !d.up_inv || !d.up_inv_sh ||
         !d.up_fac || !d.dn_inv || !d.dn_inv_sh || !d.dn_fac || !d.pinv || !d.pinv_sh || !d.pmod || !d.cdt)
         return fail(c, LC_ENOMEM, "could not upload parameter tables");

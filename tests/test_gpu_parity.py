@@ -93,6 +93,61 @@ def test_ntt_mixed_degree_chain(torch, L, oracle_mod):
             assert np.array_equal(down(g)[c], ora.poly_ntt(x[c]))
 
 
+def test_ntt_micro_workload_sampled(torch, L, oracle_mod):
+    """The mixed-degree micro-workload at full size, in the launch
+    configuration bench.py times: sampled polys of every degree against the
+    oracle, the inverse restoring every poly exactly, the same bits with the
+    two passes run per sub-batch."""
+    import bench
+    O = oracle_mod
+    ctxs = bench.d4_contexts(L)
+    polys = bench.d4_polys(torch, ctxs, 4004)
+    keep = [(x.clone(), None if y is None else y.clone()) for x, y in polys]
+    bench.d4_ntt(ctxs, polys)
+    for ctx, (x, y), (a, b), (ln, cnt, nq, k) in zip(ctxs, polys, keep, bench.D4):
+        ora = O.Oracle(ln, (50,) * nq, (50,) * k, log_m=17)
+        assert ora.primes == ctx.moduli
+        g = x.shape[0]
+        for grp in (0, g // 2, g - 1):
+            src, got = down(a[grp]), down(x[grp])
+            for l in (0, nq - 1):
+                assert np.array_equal(got[l], ora.poly_ntt(src[l:l + 1], l)[0]), (ln, grp, l)
+        if y is not None:
+            src, got = down(b[0]), down(y[0])
+            r = src.shape[0]
+            assert np.array_equal(got[r - 1], ora.poly_ntt(src[r - 1:r], r - 1)[0]), (ln, "tail")
+    fwd = [(x.clone(), None if y is None else y.clone()) for x, y in polys]
+    bench.d4_ntt(ctxs, polys, inverse=True)
+    for (x, y), (a, b) in zip(polys, keep):
+        assert torch.equal(x, a) and (y is None or torch.equal(y, b))
+    for c in ctxs:
+        c.set_tuning("ntt_sub_kb", 32768)
+    bench.d4_ntt(ctxs, polys)
+    for (x, y), (a, b) in zip(polys, fwd):
+        assert torch.equal(x, a) and (y is None or torch.equal(y, b))
+
+
+def test_hoisted_keyswitch_micro_sampled(torch, L, oracle_mod):
+    """dnum = 3 hoisted rotations of the micro-workload's c1's (2^12 and
+    2^14 chains, all log2(N/2) steps) against the oracle on sampled c1's."""
+    import bench
+    O = oracle_mod
+    for ln, cnt, nq, k in bench.D4[:2]:
+        ctx = L.Context(ln, (50,) * nq, (50,) * k, log_m=17, device=0)
+        ora = O.Oracle(ln, (50,) * nq, (50,) * k, log_m=17)
+        assert ctx.dnum == 3
+        steps = bench.d4_rotation_steps(ln)
+        ctx.keygen(4104)
+        ctx.keygen_rotation(4104, steps)
+        s = ora.secret(4104)
+        rks = [ora.rot_key(4104, s, t) for t in steps]
+        ct = synth.uniform_residues(ln, ctx.q, (6, 2, ctx.N))
+        out = down(ctx.rotate_hoisted(up(torch, ct), steps))
+        for c in (0, 5):
+            want = ora.rotate_hoisted(ct[c], steps, rks)
+            assert np.array_equal(out[c], want), (ln, c)
+
+
 # ---- keys, encryption, decryption ---------------------------------------------
 
 @pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
@@ -153,6 +208,21 @@ def test_elementwise_bitexact(torch, L, oracle_mod, prm):
     masks = np.stack([ora.signed_to_ntt(np.array([w] + [0] * (ctx.N - 1))) for w in (0, 1, 5)])
     ms = down(ctx.masked_sum(up(torch, client_cts), up(torch, masks)))
     assert np.array_equal(ms, ora.masked_sum(client_cts, masks))
+
+
+@pytest.mark.parametrize("log_n,n,ln", [(6, 11, 9), (9, 8, 8), (12, 17, 3)])
+def test_masked_sum_shapes_bitexact(torch, L, oracle_mod, log_n, n, ln):
+    """Masked aggregation with full-range masks: client groups of 8 with a
+    ragged last group, (k, comp) row blocks with a ragged last block, and a
+    limb-coefficient range that ends inside a workgroup (N = 2^6)."""
+    O = oracle_mod
+    prm = (log_n, (50, 45, 40), (50,))
+    ctx = L.Context(*prm, device=0)
+    ora = O.Oracle(*prm)
+    cts = synth.uniform_residues(300 + n, ctx.q, (n, ln, 2, ctx.N))
+    masks = synth.uniform_residues(400 + n, ctx.q, (n, ctx.N))
+    got = down(ctx.masked_sum(up(torch, cts), up(torch, masks)))
+    assert np.array_equal(got, ora.masked_sum(cts, masks))
 
 
 # ---- key switching ---------------------------------------------------------------
@@ -226,6 +296,9 @@ TINY_W5 = synth.small_workload(log_n=6, q_bits=(50, 45, 45, 45), p_bits=(50, 50)
                                scale_log2=35, name="tiny5")
 TWO_W = synth.small_workload(log_n=6, q_bits=(50, 45, 45), p_bits=(50,), n_clients=2, dim=32, scale_log2=30,
                              name="two-clients-one-ct")
+# N = 2^10 (the two-pass NTT), 4 limbs in 2 digits, 3 clients x 2 ciphertexts
+KS_W = synth.small_workload(log_n=10, q_bits=(50, 45, 45, 45), p_bits=(50, 50), n_clients=3, dim=700,
+                            scale_log2=35, name="ks-tuning")
 
 
 @pytest.mark.parametrize("w", [TINY_W, TINY_W5, TWO_W, synth.CFG1], ids=lambda w: w.name)
@@ -269,6 +342,74 @@ def test_pair_triples_many_clients(torch, L, oracle_mod, n, ln):
             if p % 7 == 0 or p == P - 1:
                 assert np.array_equal(got[p], ora.pair_triple(cts, i, j)), (i, j)
             p += 1
+
+
+@pytest.mark.parametrize("lanes,ppt", [(8, 1), (16, 3), (16, 4), (32, 6), (64, 6)])
+def test_pair_tuning_shapes_bitexact(torch, L, oracle_mod, lanes, ppt):
+    """Every pair-kernel launch shape gives the oracle's bits (13 clients:
+    78 pairs, so more than one pair per lane; 6 ciphertexts: a ragged LDS
+    batch)."""
+    O = oracle_mod
+    prm = (6, (50, 45, 40), (50,))
+    ctx = L.Context(*prm, device=0)
+    ora = O.Oracle(*prm)
+    n, ln = 13, 6
+    cts = synth.uniform_residues(77, ctx.q, (n, ln, 2, ctx.N))
+    ctx.set_tuning("pair_lanes", lanes)
+    ctx.set_tuning("pair_ppt", ppt)
+    got = down(ctx.pair_triples(up(torch, cts)))
+    p = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if p % 5 == 0 or p == n * (n - 1) // 2 - 1:
+                assert np.array_equal(got[p], ora.pair_triple(cts, i, j)), (lanes, ppt, i, j)
+            p += 1
+
+
+@pytest.mark.parametrize("log_n", [12, 16])
+def test_ntt_sub_batches_bitexact(torch, L, oracle_mod, log_n):
+    """Two-pass NTTs run per sub-batch (64 KiB: one limb group at a time) give the same bits as the whole batch and the oracle."""
+    O = oracle_mod
+    qb, pb = (50, 50, 40), (50, 45)
+    ctx = L.Context(log_n, qb, pb, device=0)
+    ora = O.Oracle(log_n, qb, pb)
+    x = synth.uniform_residues(2000 + log_n, ctx.moduli, (5, 1 << log_n))
+    ctx.set_tuning("ntt_sub_kb", 64)
+    g = up(torch, x)
+    ctx.ntt_fwd(g, nlimb=ctx.ne)
+    got = down(g)
+    for c in (0, 4):
+        want = np.vstack([ora.poly_ntt(x[c][l:l + 1], l) for l in range(ctx.ne)])
+        assert np.array_equal(got[c], want), c
+    ctx.ntt_inv(g, nlimb=ctx.ne)
+    assert np.array_equal(down(g), x)
+
+
+def test_ks_tuning_bitexact(torch, L, oracle_mod):
+    """The pipeline's key switches with one- and three-ciphertext chunks and
+    tiny NTT sub-batches (whole digit groups with own-digit limbs skipped)
+    give the oracle's bits."""
+    O = oracle_mod
+    w = KS_W
+    ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    steps = ora0.rotsum_steps(w.rot_plan)
+    ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
+    upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
+    res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps])
+    for chunk, sub, mac in ((1, 64, 8), (3, 64, 16), (64, 0, 16), (64, 0, 8)):
+        ctx.set_tuning("ks_chunk", chunk)
+        ctx.set_tuning("ntt_sub_kb", sub)
+        ctx.set_tuning("mac_cts", mac)
+        dist = ctx.pairwise_sqdist(up(torch, cts), plan=list(w.rot_plan))
+        assert np.array_equal(down(dist), res["dist"]), (chunk, sub)
+
+
+def test_set_tuning_rejects_bad_values(L):
+    ctx = L.Context(5, (30, 28, 28), (30,), device=0)
+    for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
+                        ("nope", 1)):
+        with pytest.raises(L.LancelotError):
+            ctx.set_tuning(name, value)
 
 
 def test_chunked_triples_and_finish(torch, L, oracle_mod):
