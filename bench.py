@@ -399,15 +399,19 @@ def main():
         srv.set_tuning("pair_lanes", best[1])
         srv.set_tuning("pair_ppt", best[2])
         tuned["pair_lanes"], tuned["pair_ppt"] = best[1], best[2]
-        if len(plans) > 1:
-            bestp = None
-            for pl in plans:
+        # hoisting plan jointly with the shortest tile cycle that the
+        # cycle-walking inner product takes (2^30: never)
+        bestp = None
+        for pl in plans:
+            for cmin in (1 << 30, 128, 16, 2):
+                srv.set_tuning("mac_cycle_min", cmin)
                 ms = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=pl, out=dist))
-                tuned.setdefault("plan_ms", {})[",".join(map(str, pl))] = ms
+                tuned.setdefault("plan_ms", {})["%s/%d" % (",".join(map(str, pl)), cmin)] = ms
                 if bestp is None or ms < bestp[0]:
-                    bestp = (ms, pl)
-            plan = bestp[1]
-        tuned["plan"] = plan
+                    bestp = (ms, pl, cmin)
+        plan = bestp[1]
+        srv.set_tuning("mac_cycle_min", bestp[2])
+        tuned["plan"], tuned["mac_cycle_min"] = plan, bestp[2]
         # key-switch inner-product width and batch, on the chosen plan (the NTT
         # sub-batch knob measured no gain at this size and stays off)
         for name, values in (("mac_cts", (8, 16)), ("ks_chunk", (32, 64, 128))):

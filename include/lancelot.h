@@ -220,7 +220,10 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * kernel), "pair_ppt" (1/3/4/6 pairs per lane), "ks_chunk" (1..256
  * ciphertexts per key-switch batch), "ntt_sub_kb" (0..4194304: two-pass NTTs
  * run both passes per sub-batch of about this many KiB; 0 = whole batch),
- * "mac_cts" (8/16 ciphertexts per lane of the key-switch inner product).
+ * "mac_cts" (8/16 ciphertexts per lane of the key-switch inner product),
+ * "mac_cycle" (1 = hoisted blocks of 3 or 7 rotations use the cycle-walking
+ * inner product that reads each raised digit once; 0 = one gather per key),
+ * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used).
  * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

@@ -277,6 +277,7 @@ int lc_keygen_rotation(lc_ctx *x, uint64_t seed, const int *steps, int nsteps)
         if ((rc = launch_permute(c, c->sk_ntt, t, perm, c->ne, 0))) return rc;
         if ((rc = gen_ksk(c, seed, g, t, k))) return rc;
         c->rot[g] = RotKey{k, perm, g};
+        if ((rc = build_cycle_table(c, g))) return rc;
     }
     return LC_OK;
 }
@@ -309,6 +310,8 @@ int lc_keys_share(const lc_ctx *xs, lc_ctx *xd)
         c->key_bytes += K * 8;
         LC_HIP(c, hipMemcpy(k, kv.second.ksk, K * 8, hipMemcpyDeviceToDevice));
         c->rot[kv.first] = RotKey{k, perm, kv.first};
+        int rc = build_cycle_table(c, kv.first);
+        if (rc) return rc;
     }
     return LC_OK;
 }
@@ -526,6 +529,9 @@ int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nb
             G.keys[t - 1] = it->second.ksk;
             G.perms[t - 1] = it->second.perm;
         }
+        // keys t 2^j0 = powers of the step-2^j0 automorphism: the cycle walk applies
+        auto cy = c->cycles.find(galois_of_step(c->log_n, 1ll << j0));
+        if (G.n > 1 && cy != c->cycles.end() && cy->second.nseg > 0) G.cyc = &cy->second;
         blocks.push_back(G);
         j0 += k;
     }
@@ -690,6 +696,12 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cts") {
         if (value != 8 && value != 16) return fail(c, LC_EINVAL, "mac_cts: 8/16");
         c->tune.mac_cts = value;
+    } else if (k == "mac_cycle") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle: 0/1");
+        c->tune.mac_cycle = value;
+    } else if (k == "mac_cycle_min") {
+        if (value < 1) return fail(c, LC_EINVAL, "mac_cycle_min: >= 1");
+        c->tune.mac_cycle_min = value;
     } else if (k == "ntt_sub_kb") {
         if (value < 0 || value > (1 << 22)) return fail(c, LC_EINVAL, "ntt_sub_kb: 0..4194304");
         c->tune.ntt_sub_kb = value;

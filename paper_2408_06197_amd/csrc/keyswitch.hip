@@ -131,6 +131,182 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
     }
 }
 
+// ---- cycle-walking inner product for a hoisted block ------------------------
+//
+// The keys of a rotate-and-sum block are the powers phi^1 .. phi^R of one
+// automorphism phi (rotations t 2^j0).  In the NTT domain phi permutes
+// coefficients so that every aligned tile of KS_CYC_TILE coefficients lands
+// inside one aligned tile; call that tile map tau.  Output tile o of key t
+// reads source tile tau^t(o).  Walking a cycle c_0, c_1 = tau(c_0), ... of
+// tau, output c_m reads c_{m+1} .. c_{m+R}, so a workgroup that walks the
+// cycle needs one new source tile per step: it stages source tile c_p (all
+// digits of MAC_CB ciphertexts, as doubles) and the keys of the R outputs
+// that read it (c_{p-1} with key 1 ... c_{p-R} with key R) in LDS, adds the
+// contributions, and writes c_{p-R}, which is then complete.  Accumulators
+// live in registers by age.  The raised digits are read about
+// (1 + (R - 1) / KS_CYC_SEG) times instead of R times, every key value once
+// per MAC_CB ciphertexts.  Short cycles re-stage the same tiles, which the
+// caches serve.  Same FP64 Barrett products and reductions as mac_kernel
+// (a reduction after every 4 products), so the same residues.
+constexpr int MAC_CB = 8;  // ciphertexts per workgroup (one per thread row)
+
+template <int R, int D>
+__global__ void __launch_bounds__(KS_CYC_TILE * MAC_CB, 3)
+mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, const CycleSeg *segs,
+                 const u32 *walk, u64 *acc, u64 count)
+{
+    constexpr int TT = KS_CYC_TILE;
+    __shared__ double xt[MAC_CB * D * TT];  // [MAC_CB][D][TT]: source tile c_p
+    __shared__ double kt[R * 2 * D * TT];   // [R][2 D][TT]: keys of the outputs c_{p-1} .. c_{p-R}
+    const int u = threadIdx.x, bl = threadIdx.y;
+    const CycleSeg sg = segs[blockIdx.x];
+    const int l = blockIdx.y;
+    const u64 b = (u64)blockIdx.z * MAC_CB + bl;
+    const bool live = b < count;
+    const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+    const int own = l < dp.nq ? l / dp.alpha : -1;
+
+    // Staging roles: thread row bl stages its ciphertext's D digit values at
+    // lane u, and (for bl < R) the 2 D key values of key bl + 1 for the
+    // output that key serves at this step.  The loads of step p + 1 are in
+    // flight while step p computes.
+    const u64 *xraised = raised + (b * D * dp.ne + l) * N + u;
+    const u64 *xown = x + b * x_stride + lN + u;
+    const u64 *ksrc = bl < R ? ks.key[bl] + lN + u : nullptr;
+    u64 xv[D], kv[2 * D];
+    auto fetch = [&](int p) {
+        const u64 src = (u64)walk[sg.base + p % sg.len] * TT;
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            xv[d] = live ? (d == own ? xown[src] : xraised[(u64)d * dp.ne * N + src]) : 0;
+        const int m = p - 1 - bl;  // output served by key bl + 1
+        const bool kl = bl < R && m >= sg.m0 && m < sg.m0 + sg.cnt;
+        const u64 dst = kl ? (u64)walk[sg.base + m % sg.len] * TT : 0;
+#pragma unroll
+        for (int dk = 0; dk < 2 * D; dk++) kv[dk] = kl ? ksrc[(u64)dk * NE + dst] : 0;
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int d = 0; d < D; d++) xt[(bl * D + d) * TT + u] = u64_to_d(xv[d]);
+        if (bl < R) {
+#pragma unroll
+            for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
+        }
+    };
+
+    double A[R][2];  // A[t - 1]: output position p - t
+#pragma unroll
+    for (int t = 0; t < R; t++) A[t][0] = A[t][1] = 0.0;
+    const int pend = sg.m0 + sg.cnt + R;
+    fetch(sg.m0 + 1);
+    for (int p = sg.m0 + 1; p < pend; p++) {
+        store();
+        __syncthreads();
+        if (p + 1 < pend) fetch(p + 1);
+#pragma unroll
+        for (int t = 1; t <= R; t++) {
+            const int m = p - t;
+            if (m >= sg.m0 && m < sg.m0 + sg.cnt) {
+                const u64 j = (u64)walk[sg.base + m % sg.len] * TT + u;
+                const double *xs = xt + bl * D * TT + (ks.perm[t - 1][j] & (TT - 1));
+                const double *kk = kt + (t - 1) * 2 * D * TT + u;
+                double a0 = A[t - 1][0], a1 = A[t - 1][1];
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    const double xd = xs[d * TT];
+                    a0 += mulmod_d(xd, kk[(2 * d) * TT], q, qinv);
+                    a1 += mulmod_d(xd, kk[(2 * d + 1) * TT], q, qinv);
+                    if ((d & 3) == 3) {
+                        a0 = reduce_d(a0, q, qinv);
+                        a1 = reduce_d(a1, q, qinv);
+                    }
+                }
+                A[t - 1][0] = reduce_d(a0, q, qinv);
+                A[t - 1][1] = reduce_d(a1, q, qinv);
+            }
+        }
+        const int mo = p - R;  // complete: its key-R contribution was just added
+        if (mo >= sg.m0 && live) {
+            const u64 j = (u64)walk[sg.base + mo % sg.len] * TT + u;
+            acc[(b * 2) * NE + lN + j] = d_to_canonical(A[R - 1][0], q, qinv);
+            acc[(b * 2 + 1) * NE + lN + j] = d_to_canonical(A[R - 1][1], q, qinv);
+        }
+#pragma unroll
+        for (int t = R - 1; t > 0; t--) {
+            A[t][0] = A[t - 1][0];
+            A[t][1] = A[t - 1][1];
+        }
+        A[0][0] = A[0][1] = 0.0;
+        __syncthreads();  // the tile is rewritten next step
+    }
+}
+
+template <int R>
+static void launch_mac_cycle(int dnum, dim3 grid, dim3 block, hipStream_t s, const DevParams &dp, const u64 *x,
+                             u64 x_stride, const u64 *raised, const KeySet &ks, const CycleTable *cyc, u64 *acc,
+                             u64 count)
+{
+    switch (dnum) {
+    case 3: hipLaunchKernelGGL((mac_cycle_kernel<R, 3>), grid, block, 0, s, dp, x, x_stride, raised, ks, cyc->segs,
+                               cyc->walk, acc, count); break;
+    case 4: hipLaunchKernelGGL((mac_cycle_kernel<R, 4>), grid, block, 0, s, dp, x, x_stride, raised, ks, cyc->segs,
+                               cyc->walk, acc, count); break;
+    default: hipLaunchKernelGGL((mac_cycle_kernel<R, 6>), grid, block, 0, s, dp, x, x_stride, raised, ks,
+                                cyc->segs, cyc->walk, acc, count); break;
+    }
+}
+
+int build_cycle_table(Ctx *c, u64 g)
+{
+    if (c->cycles.count(g)) return LC_OK;
+    CycleTable tab;
+    const u64 N = c->N, TT = KS_CYC_TILE;
+    if (c->device >= 0 && N >= TT) {
+        const std::vector<u32> perm = automorphism_perm(c->log_n, g);
+        const u64 nt = N / TT;
+        std::vector<u32> tau(nt);
+        bool tiles = true;
+        for (u64 o = 0; o < nt && tiles; o++) {
+            tau[o] = perm[o * TT] / (u32)TT;
+            for (u64 v = 1; v < TT; v++)
+                if (perm[o * TT + v] / TT != tau[o]) tiles = false;
+        }
+        if (tiles) {
+            std::vector<u32> walk;
+            std::vector<CycleSeg> segs;
+            std::vector<char> seen(nt, 0);
+            int min_len = (int)nt;
+            for (u64 o = 0; o < nt; o++) {
+                if (seen[o]) continue;
+                const int base = (int)walk.size();
+                for (u32 t = (u32)o; !seen[t]; t = tau[t]) {
+                    seen[t] = 1;
+                    walk.push_back(t);
+                }
+                const int len = (int)walk.size() - base;
+                min_len = std::min(min_len, len);
+                for (int m0 = 0; m0 < len; m0 += KS_CYC_SEG)
+                    segs.push_back(CycleSeg{base, len, m0, std::min(KS_CYC_SEG, len - m0)});
+            }
+            if (walk.size() == nt) {  // tau is a permutation of the tiles
+                u32 *dw = (u32 *)dev_alloc(c, walk.size() * sizeof(u32));
+                CycleSeg *ds = (CycleSeg *)dev_alloc(c, segs.size() * sizeof(CycleSeg));
+                if (!dw || !ds) return fail(c, LC_ENOMEM, "cycle table allocation failed");
+                LC_HIP(c, hipMemcpy(dw, walk.data(), walk.size() * sizeof(u32), hipMemcpyHostToDevice));
+                LC_HIP(c, hipMemcpy(ds, segs.data(), segs.size() * sizeof(CycleSeg), hipMemcpyHostToDevice));
+                c->table_bytes += walk.size() * sizeof(u32) + segs.size() * sizeof(CycleSeg);
+                tab.walk = dw;
+                tab.segs = ds;
+                tab.nseg = (int)segs.size();
+                tab.min_len = min_len;
+            }
+        }
+    }
+    c->cycles[g] = tab;
+    return LC_OK;
+}
+
 // v[b][k][l][j] = BConv_{P->Q} of the (coefficient-domain) P limbs of acc,
 // in the same FP64 form as the ModUp conversion.
 __global__ void __launch_bounds__(KS_THREADS)
@@ -227,7 +403,15 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                 ks.key[t] = G.keys[t];
                 ks.perm[t] = G.perms[t];
             }
-            if (c->tune.mac_cts == 16)
+            // the walk pays off on long cycles; on short ones the per-key gathers
+            // of mac_kernel hit the same few tiles in cache
+            const bool cyc = c->tune.mac_cycle && G.cyc && G.cyc->nseg > 0 && (G.n == 3 || G.n == 7) &&
+                             (dnum == 3 || dnum == 4 || dnum == 6) && G.cyc->min_len >= c->tune.mac_cycle_min;
+            if (cyc) {
+                dim3 grid((u32)G.cyc->nseg, (u32)ne, (u32)((B + MAC_CB - 1) / MAC_CB)), block(KS_CYC_TILE, MAC_CB);
+                if (G.n == 3) launch_mac_cycle<3>(dnum, grid, block, s, c->dp, xb, x_stride, raised, ks, G.cyc, acc, B);
+                else launch_mac_cycle<7>(dnum, grid, block, s, c->dp, xb, x_stride, raised, ks, G.cyc, acc, B);
+            } else if (c->tune.mac_cts == 16)
                 hipLaunchKernelGGL((mac_kernel<16>), dim3(blocks_for((u64)ne * N), (u32)((B + 15) / 16)),
                                    dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
             else

@@ -37,6 +37,23 @@ struct DevParams {
     const u64 *cdt;                 // [38]: Gaussian thresholds
 };
 
+// Cycle walk of an automorphism's tile map (the cycle-walking key-switch
+// inner product): with tiles of KS_CYC_TILE coefficients, the NTT-domain
+// permutation of a Galois element maps every aligned tile onto one aligned
+// tile.  `walk` lists the tiles cycle by cycle in map order; segment s covers
+// output positions m0 .. m0 + cnt - 1 of the cycle at walk[base .. base + len).
+constexpr int KS_CYC_TILE = 32;
+constexpr int KS_CYC_SEG = 32;
+struct CycleSeg {
+    int base, len, m0, cnt;
+};
+struct CycleTable {
+    const CycleSeg *segs = nullptr;
+    const u32 *walk = nullptr;
+    int nseg = 0;     // 0: the map does not act on tiles (N below the tile size)
+    int min_len = 0;  // shortest cycle (all cycles have one length for a power of 5)
+};
+
 struct RotKey {
     u64 *ksk = nullptr;    // [dnum][2][ne][N]
     u32 *perm = nullptr;   // [N]: NTT-domain index map of the automorphism
@@ -75,6 +92,7 @@ struct Ctx {
         size_t bytes[8] = {};
     };
     std::map<hipStream_t, Workspace> ws;
+    std::map<u64, CycleTable> cycles;  // by Galois element
     size_t ws_limit = 0;
 
     // launch-shape tuning (lc_set_tuning)
@@ -84,6 +102,8 @@ struct Ctx {
         int ks_chunk = 64;    // ciphertexts per key-switch batch
         int ntt_sub_kb = 0;   // two-pass NTTs run per sub-batch of this many KiB (0: whole batch)
         int mac_cts = 8;      // ciphertexts per lane of the key-switch inner product (8 or 16)
+        int mac_cycle = 1;    // hoisted blocks of 3 or 7 keys use the cycle-walking inner product ...
+        int mac_cycle_min = 16;  // ... when the tile cycles are at least this long
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
 };
@@ -164,6 +184,7 @@ struct KsGroup {
     const u64 *keys[8];
     const u32 *perms[8];  // NULL = identity
     int n;
+    const CycleTable *cyc;  // optional: keys t = 1..n are the powers phi^t of one automorphism with this walk
     const u64 *base;      // optional [2][nq][N] added to the output (stride per ct)
     u64 base_stride;
     const u64 *c0src;     // optional: sum_t phi_t(c0src) added to component 0
@@ -176,5 +197,8 @@ struct KsGroup {
 int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
                       hipStream_t s);
 u64 ks_words_per_ct(const Ctx *c);
+// Builds (once, at key set-up: it copies to the device synchronously) the
+// tile-cycle walk of Galois element g.
+int build_cycle_table(Ctx *c, u64 g);
 
 }  // namespace lc

@@ -275,6 +275,51 @@ def test_rotate_sum_bitexact(torch, L, oracle_mod, prm, plan):
         assert np.array_equal(got[c], want), c
 
 
+@pytest.mark.parametrize("prm,plan", [(CFG1, (3, 3, 3, 2)), (CFG1, (2, 3, 3, 3)), (TINY_A2, (3, 2))],
+                         ids=["n4096-3332", "n4096-2333", "n64-32"])
+def test_rotate_sum_cycle_walk_bitexact(torch, L, oracle_mod, prm, plan):
+    """Blocks of 3 and 7 rotations through the cycle-walking inner product
+    (walks of the tile map up to 64 tiles long at N = 2^12; one tile at
+    N = 64) and through the per-key gather, both equal to the oracle."""
+    O = oracle_mod
+    plan = list(plan)
+    ora0 = O.Oracle(*prm)
+    steps = ora0.rotsum_steps(plan)
+    ctx, ora, keys = make_pair(L, O, *prm, seed=19, steps=steps)
+    rng = np.random.default_rng(9)
+    m = rng.integers(-(1 << 20), 1 << 20, size=(11, ctx.N), dtype=np.int64)  # 11: a ragged group of 8
+    cts = ora.encrypt(5, 0, m, keys["pk"])
+    want = [ora.rotate_sum(cts[c], plan, [keys["rot"][k] for k in steps]) for c in (0, 7, 10)]
+    ctx.set_tuning("mac_cycle_min", 1)  # every block walks, even one-tile cycles
+    for cyc in (1, 0):
+        ctx.set_tuning("mac_cycle", cyc)
+        g = up(torch, cts)
+        ctx.rotate_sum(g, plan)
+        got = down(g)
+        for w, c in zip(want, (0, 7, 10)):
+            assert np.array_equal(got[c], w), (cyc, c)
+
+
+def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
+    """N = 2^16, 24 + 4 limbs (dnum 6), the (3,3,3,3,3) plan that the bench
+    autotunes to: cycles of the tile map up to 1024 tiles, several segments
+    per cycle; two ciphertexts against the oracle."""
+    O = oracle_mod
+    prm = (16, (50,) * 24, (50,) * 4)
+    plan = [3, 3, 3, 3, 3]
+    ora0 = O.Oracle(*prm)
+    steps = ora0.rotsum_steps(plan)
+    ctx, ora, keys = make_pair(L, O, *prm, seed=23, steps=steps)
+    ctx.set_tuning("mac_cycle_min", 1)
+    cts = synth.uniform_residues(24, ctx.q, (2, 2, ctx.N))
+    g = up(torch, cts)
+    ctx.rotate_sum(g, plan)
+    got = down(g)
+    rks = [keys["rot"][k] for k in steps]
+    for c in range(2):
+        assert np.array_equal(got[c], ora.rotate_sum(cts[c], plan, rks)), c
+
+
 # ---- the pairwise pipeline -----------------------------------------------------------
 
 def encrypt_workload(O, ora, keys, w, seed):
@@ -407,7 +452,7 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
 def test_set_tuning_rejects_bad_values(L):
     ctx = L.Context(5, (30, 28, 28), (30,), device=0)
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
-                        ("nope", 1)):
+                        ("mac_cycle", 2), ("mac_cycle_min", 0), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
