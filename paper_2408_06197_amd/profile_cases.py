@@ -1,0 +1,67 @@
+"""Small fixed GPU cases for hardware-counter runs (rocprofv3 --pmc).
+
+    python -m paper_2408_06197_amd.profile_cases pair       # one pair-triple launch
+    python -m paper_2408_06197_amd.profile_cases keyswitch  # one rotate-and-sum of 16 ciphertexts
+
+Both run at N = 2^16 with 24 + 4 limbs of 50 bits on random residues, then
+copy 4 GiB with a plain device copy so that each counter can be scaled by
+what it reads for a copy of known size.  Counter passes each need a run of
+their own (rocprofv3 does not split counters over passes).
+"""
+from __future__ import annotations
+
+import sys
+
+import torch
+
+from . import lancelot as L
+
+NQ, NP, LOG_N = 24, 4, 16
+
+
+def _calibration_copy():
+    src = torch.ones(1 << 29, dtype=torch.int64, device="cuda")  # 4 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def pair(lanes=16, ppt=6, n=20, ln=342):
+    """lc_pair_triples over 20 clients x 342 packed ciphertexts (172 GB)."""
+    ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    cts = torch.empty((n, ln, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    for i in range(n):
+        cts[i].random_(0, 1 << 49, generator=gen)  # below every 50-bit prime
+    trip = torch.empty((n * (n - 1) // 2, 3, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    ctx.set_tuning("pair_lanes", lanes)
+    ctx.set_tuning("pair_ppt", ppt)
+    ctx.pair_triples(cts, out=trip)
+    torch.cuda.synchronize()
+    del cts
+    _calibration_copy()
+
+
+def keyswitch(count=16, plan=(3, 3, 3, 3, 3)):
+    """lc_rotate_sum of `count` ciphertexts with the given hoisting plan."""
+    ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
+    ctx.keygen(7)
+    ctx.keygen_rotation(7, ctx.rotsum_steps(list(plan)))
+    ctx.set_tuning("ks_chunk", count)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    ct = torch.empty((count, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    ct.random_(0, 1 << 49, generator=gen)
+    ctx.rotate_sum(ct, list(plan))
+    torch.cuda.synchronize()
+    _calibration_copy()
+
+
+if __name__ == "__main__":
+    case = sys.argv[1] if len(sys.argv) > 1 else "pair"
+    if case not in ("pair", "keyswitch"):
+        sys.exit("cases: pair, keyswitch")
+    torch.cuda.set_device(0)
+    {"pair": pair, "keyswitch": keyswitch}[case]()
+    print(f"profile case {case} done", flush=True)
