@@ -23,6 +23,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# rounds of very different sizes share the device in the serving form:
+# growable segments keep torch's cache from fragmenting (set before torch loads)
+os.environ.setdefault("PYTORCH_ALLOC_CONF", "expandable_segments:True")
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # FP64 lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz (78.6 TFLOP/s)
@@ -65,6 +68,10 @@ def parse():
     p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
     p.add_argument("--no-graph", dest="graph", action="store_false", default=True,
                    help="time eager launches instead of a captured HIP graph")
+    p.add_argument("--no-round", dest="round", action="store_false", default=True,
+                   help="skip the selection / encrypted-mask aggregation / model decryption of the round")
+    p.add_argument("--no-ablation", dest="ablation", action="store_false", default=True,
+                   help="skip the lazy/eager relinearization and per-client SumDis ablations")
     p.add_argument("--no-ntt-micro", dest="ntt_micro", action="store_false", default=True,
                    help="skip the mixed-degree NTT / hoisted key-switch micro-workload")
     p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
@@ -289,14 +296,21 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     log(f"[bench] serving: pools encoded in {time.perf_counter() - t0:.1f}s")
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    # leave room for the library's per-stream scratch (key switching, rotation
-    # ping-pong, encryption staging: about 10 GB per stream) and torch's cache
-    budget = int(free * 0.5)
+    # leave room for the library's per-stream scratch at N=2^16 (key-switch
+    # batch of 32: 5 GB; rotation ping-pong and encryption staging: up to
+    # 3 GB) and for torch's cache
+    budget = int(0.5 * (free - args.serve_slots * 8 * 2 ** 30))
     names = list(chains)
+
+    def progress(k, rec):
+        if k % 25 == 0:
+            log(f"[bench] serving: {k} rounds done (last: n={rec['n']} dim={rec['dim']} {rec['chain']}, "
+                f"latency {rec['latency']:.3f}s)")
 
     def run(specs):
         ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=k_chunk, streams=args.serve_slots)
-        return serve.Scheduler(chains, budget, slots=args.serve_slots, k_chunk=k_chunk).run(specs, ex)
+        return serve.Scheduler(chains, budget, slots=args.serve_slots, k_chunk=k_chunk).run(specs, ex,
+                                                                                          on_done=progress)
 
     # closed-loop calibration: a burst of rounds arriving together
     calib = serve.make_stream(8, rate=0.0, chains=names, seed=2999)
@@ -313,9 +327,9 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     rec = run(specs)
     wall = time.perf_counter() - t0
     st = serve.latency_stats(rec)
-    # spot-check decryption of a few rounds against FP64
+    # every tenth round's decrypted distances against FP64
     errs = []
-    for rid in list(rec)[:6]:
+    for rid in sorted(r for r in rec if r % 10 == 0):
         sp = specs[rid]
         ref = serve.reference_distances(sp, pools[sp.chain], chains[sp.chain].n_ct(sp.dim))
         got = rec[rid]["result"]["distances"]
@@ -501,7 +515,48 @@ def main():
     log(f"[bench] decrypted distances vs FP64: max rel err {rel.max():.2e} over {P} pairs")
     check = {"max_rel_err_vs_fp64": float(rel.max()), "pairs": P, "ok": bool(rel.max() < 1e-4)}
 
+    # ---- the rest of the round (Algorithm 1: KGC selection and encrypted mask,
+    # ServerUpdate): Multi-Krum on the decrypted distances, Enc_pk of each
+    # client's weight 1/l (or 0) at scale Delta, the masked aggregation of all
+    # packed ciphertexts with one relinearization each, and the KGC's
+    # decryption of the aggregated model (first and last ciphertext checked
+    # against the FP64 mean of the chosen updates)
     extra = {}
+    if args.round:
+        from paper_2408_06197_amd import robust
+        t_sel0 = time.perf_counter()
+        c_byz = w.n_byz
+        chosen = robust.select("multikrum", robust.distance_matrix(got, n), c_byz, l=n - c_byz)
+        t_sel = time.perf_counter() - t_sel0
+        chosen_fp64 = robust.select("multikrum", robust.distance_matrix(ref, n), c_byz, l=n - c_byz)
+        wts = robust.weights("multikrum", chosen, n)
+        m_mask = torch.from_numpy(robust.mask_plaintexts(wts, N, scale)).cuda()
+        mask_ct = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
+        t_mask = event_time(torch, lambda: kgc.encrypt(m_mask, seed=w.crypto_seed + 7, first_object=1 << 40,
+                                                        out=mask_ct))
+        agg2 = torch.empty((ln, 2, nq, N), dtype=torch.int64, device="cuda")
+        t_agg = event_time(torch, lambda: srv.mask_aggregate(cts, mask_ct, out=agg2))
+        dec_agg = torch.empty((ln, nq, N), dtype=torch.int64, device="cuda")
+        t_dec_agg = event_time(torch, lambda: kgc.decrypt(agg2, out=dec_agg))
+        errs = []
+        for k in (0, ln - 1):
+            z = kgc.decode(dec_agg[k].cpu().numpy().view(np.uint64), scale * scale).real
+            lo, hi = k * w.slots, min((k + 1) * w.slots, w.dim)
+            want = np.zeros(w.slots)
+            for i in chosen:
+                want[: hi - lo] += synth.client_updates(w, clients=[i])[0][lo:hi] / len(chosen)
+            errs.append(float(np.max(np.abs(z - want))))
+        del agg2, dec_agg, mask_ct, m_mask
+        extra["round"] = {"rule": "multikrum", "c": c_byz, "l": n - c_byz, "chosen": chosen,
+                          "same_as_fp64_selection": chosen == chosen_fp64,
+                          "byzantine_chosen": int(sum(i >= n - c_byz for i in chosen)),
+                          "kgc_select_ms": t_sel * 1e3, "mask_encrypt_ms": t_mask, "mask_aggregate_ms": t_agg,
+                          "decrypt_model_ms": t_dec_agg, "max_abs_err_vs_fp64_mean": max(errs),
+                          "update_std": w.std}
+        log(f"[bench] round: Multi-Krum chose {len(chosen)} clients ({extra['round']['byzantine_chosen']} "
+            f"Byzantine; same as FP64: {chosen == chosen_fp64}); mask encrypt {t_mask:.1f} ms, aggregate "
+            f"{t_agg:.1f} ms, model decrypt {t_dec_agg:.1f} ms; max |err| vs FP64 mean {max(errs):.2e}")
+
     if args.stages:
         trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
         t_a2 = event_time(torch, lambda: srv.pair_triples(cts, out=trip))
@@ -540,6 +595,77 @@ def main():
                                 "distances_per_s": len(pairs) / tp}
         log(f"[bench] per-op form: {tp / len(pairs) * 1e3:.1f} ms/pair -> {len(pairs) / tp:.2f} distances/s")
 
+    # ---- ablations of the paper's two techniques (Lazy Relinearization, Dynamic Hoisting) ----------
+    if args.ablation:
+        ab = {"hoisting_plan_ms": {k: v for k, v in tuned.get("plan_ms", {}).items()}}
+        # eager relinearization in the per-op form, one pair: relinearize every
+        # square, then add the 2-component results (LEN key switches per pair
+        # instead of one)
+        i0, j0 = 0, n - 1
+        tmp = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+        sq = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+        r2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+        acc2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+        acc3 = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+        out2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+
+        def eager():
+            acc2.zero_()
+            for k in range(ln):
+                srv.ct_sub(cts[i0, k], cts[j0, k], out=tmp)
+                srv.ct_square(tmp, out=sq)
+                srv.relin(sq, out=r2)
+                srv.ct_add(acc2, r2, out=acc2)
+            srv.rotate_sum(acc2, plan)
+
+        def lazy():
+            acc3.zero_()
+            for k in range(ln):
+                srv.ct_sub(cts[i0, k], cts[j0, k], out=tmp)
+                srv.ct_square(tmp, out=sq)
+                srv.ct_add(acc3, sq, out=acc3, ncomp=3)
+            srv.relin(acc3, out=out2)
+            srv.rotate_sum(out2, plan)
+
+        t_eager = event_time(torch, eager)
+        t_lazy = event_time(torch, lazy)
+        d_e = kgc.crt_to_double(kgc.decrypt(acc2)[0, :, :1].cpu().numpy().view(np.uint64))[0] / scale ** 2
+        d_l = kgc.crt_to_double(kgc.decrypt(out2)[0, :, :1].cpu().numpy().view(np.uint64))[0] / scale ** 2
+        ab["relin_per_op_one_pair"] = {"eager_ms": t_eager, "lazy_ms": t_lazy, "speedup": t_eager / t_lazy,
+                                       "key_switches_eager": ln + len(plan), "key_switches_lazy": 1 + len(plan),
+                                       "distance_eager": d_e, "distance_lazy": d_l}
+        del tmp, sq, r2, acc2, acc3, out2
+        # SumDis with one relinearization and rotate-and-sum per client: the
+        # triples of all pairs (i, j) are summed per client i first (n key
+        # switch chains instead of P)
+        trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
+        sums = torch.empty((n, 3, nq, N), dtype=torch.int64, device="cuda")
+        s2 = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
+        pidx = [(a, b) for a in range(n) for b in range(a + 1, n)]
+
+        def sumdis_lazy():
+            srv.pair_triples(cts, out=trip)
+            sums.zero_()
+            for p_, (a, b) in enumerate(pidx):
+                srv.ct_add(sums[a], trip[p_], out=sums[a], ncomp=3)
+                srv.ct_add(sums[b], trip[p_], out=sums[b], ncomp=3)
+            srv.relin(sums, out=s2)
+            srv.rotate_sum(s2, plan)
+
+        t_sd = event_time(torch, sumdis_lazy)
+        del trip, sums
+        t_full = extra["stage_ms"]["pairwise_total"] if "stage_ms" in extra else None
+        ds = kgc.crt_to_double(kgc.decrypt(s2)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()) / scale ** 2
+        dref = kgc.crt_to_double(kgc.decrypt(sumdis)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()) / scale ** 2
+        ab["sumdis_per_client_relin"] = {"ms": t_sd, "pairwise_with_sumdis_ms": t_full,
+                                        "key_switch_chains": n, "vs_pairwise_chains": P,
+                                        "max_rel_diff_vs_pairwise_sumdis": float(np.max(np.abs(ds - dref) / np.abs(dref)))}
+        del s2
+        extra["ablation"] = ab
+        log(f"[bench] ablation: eager relin {t_eager:.0f} ms vs lazy {t_lazy:.0f} ms per pair "
+            f"({t_eager / t_lazy:.1f}x); SumDis with per-client relin {t_sd:.0f} ms "
+            f"(max rel diff {ab['sumdis_per_client_relin']['max_rel_diff_vs_pairwise_sumdis']:.1e})")
+
     # ---- roofline of the dominant kernel ------------------------------------------
     # Candidates: the fused pair-triple kernel (one launch per step, FP64-ALU
     # bound: 23 FP64 lane-instructions per update in the Barrett form -- two
@@ -576,6 +702,9 @@ def main():
     # the round's ciphertexts are no longer needed
     used_graph = graph is not None
     del cts, dist, sumdis, agg, dec, masks, graph
+    torch.cuda.synchronize()
+    for ctx_ in (srv, kgc):  # the graph is gone: give back the timed stream's workspaces
+        ctx_.release_workspace()
     torch.cuda.empty_cache()
 
     if args.ntt_micro:

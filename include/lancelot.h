@@ -18,12 +18,15 @@
  * Ownership.  The caller allocates and frees every buffer it passes; a
  *   pointer argument named *_dev is device memory on the context's device,
  *   *_host is host memory.  The library owns its parameter tables, resident
- *   keys and a workspace it grows on demand (hipMalloc) and frees at
- *   lc_ctx_destroy.
+ *   keys and a workspace per stream that it grows on demand (hipMalloc);
+ *   an outgrown workspace buffer is kept until lc_ctx_destroy, so work
+ *   captured into a HIP graph earlier keeps valid memory.
  * Streams.  `stream` is a hipStream_t (NULL: the default stream).  Device
  *   calls are asynchronous on it; lc_sync waits and reports asynchronous
- *   errors.  Calls on one context must come from one host thread at a time;
- *   growing a stream's workspace waits for that stream.
+ *   errors.  Calls on one context must come from one host thread at a time.
+ *   Once a stream's workspace has grown to a call's size, that call on that
+ *   stream allocates, copies and synchronizes nothing (it can be captured
+ *   into a HIP graph; replays share the stream's workspace).
  * Errors.  Every call returns LC_OK (0) or a negative code; lc_last_error
  *   gives text.  Nothing is written to outputs when a call returns an error
  *   before launching work.
@@ -80,6 +83,10 @@ int lc_ctx_moduli(const lc_ctx *ctx, uint64_t *moduli_host);
 /* Any pointer may be NULL. */
 int lc_ctx_info(const lc_ctx *ctx, int *log_n, int *n_q, int *n_p, int *dnum);
 int lc_sync(lc_ctx *ctx, void *stream);
+/* Waits for the device and frees every workspace of the context (outgrown
+ * ones included); later calls grow them again.  HIP graphs captured before
+ * must not be replayed afterwards. */
+int lc_release_workspace(lc_ctx *ctx);
 /* Bytes of library-owned device memory (tables, keys, workspace). */
 int lc_ctx_device_bytes(const lc_ctx *ctx, size_t *bytes);
 
@@ -199,6 +206,17 @@ int lc_pairwise_finish(lc_ctx *ctx, const uint64_t *triples_dev, int n, const in
 int lc_pairwise_sqdist(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const int *plan, int nblocks,
                        uint64_t *dist_dev, uint64_t *sumdis_dev, void *stream);
 
+/* ServerUpdate with an encrypted mask (Algorithm 1, ServerUpdate; Methods,
+ * Masked-based Encrypted Sorting): out[k] = relin(sum_i ct_i[k] (x) M_i),
+ * the client ciphertexts [n][len][2][n_q][N] times each client's mask
+ * ciphertext M_i = Enc_pk(weight_i) ([n][2][n_q][N], NTT domain), summed
+ * over clients before one relinearization per packed ciphertext (lazy).
+ * out [len][2][n_q][N] must not overlap the inputs (LC_EINVAL); needs the
+ * relinearization key (LC_EKEY).  The result is at the product of the two
+ * scales. */
+int lc_mask_aggregate(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const uint64_t *mask_cts_dev,
+                      uint64_t *out_dev, void *stream);
+
 /* ---- transforms ------------------------------------------------------------ */
 
 /* In-place negacyclic NTT / inverse NTT of count polynomials of nlimb limbs
@@ -223,7 +241,9 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * "mac_cts" (8/16 ciphertexts per lane of the key-switch inner product),
  * "mac_cycle" (1 = hoisted blocks of 3 or 7 rotations use the cycle-walking
  * inner product that reads each raised digit once; 0 = one gather per key),
- * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used).
+ * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used),
+ * "fuse_modup" (1 = for 2^10 <= N the ModUp base conversion runs inside the
+ * first forward-NTT pass of the raised digits; 0 = a kernel of its own).
  * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

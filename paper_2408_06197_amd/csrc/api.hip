@@ -32,8 +32,10 @@ u64 *ws_get(Ctx *c, int slot, size_t bytes, hipStream_t s)
     Ctx::Workspace &w = c->ws[s];
     if (w.bytes[slot] >= bytes && w.slot[slot]) return (u64 *)w.slot[slot];
     if (w.slot[slot]) {
-        hipStreamSynchronize(s);
-        hipFree(w.slot[slot]);
+        // a HIP graph captured on this stream may still name the old buffer:
+        // retire it (freed with the context) rather than free it now
+        c->retired.push_back(w.slot[slot]);
+        c->retired_bytes += w.bytes[slot];
         w.slot[slot] = nullptr;
         w.bytes[slot] = 0;
     }
@@ -159,6 +161,7 @@ int lc_ctx_destroy(lc_ctx *x)
         hipSetDevice(c->device);
         hipDeviceSynchronize();
         for (void *p : c->allocs) hipFree(p);
+        for (void *p : c->retired) hipFree(p);
         for (auto &kv : c->ws)
             for (int i = 0; i < 8; i++)
                 if (kv.second.slot[i]) hipFree(kv.second.slot[i]);
@@ -194,10 +197,29 @@ int lc_sync(lc_ctx *x, void *stream)
     return LC_OK;
 }
 
+int lc_release_workspace(lc_ctx *x)
+{
+    CHECK_CTX(x);
+    if (c->device < 0) return LC_OK;
+    LC_HIP(c, hipDeviceSynchronize());
+    for (void *p : c->retired) hipFree(p);
+    c->retired.clear();
+    c->retired_bytes = 0;
+    for (auto &kv : c->ws)
+        for (int i = 0; i < 8; i++)
+            if (kv.second.slot[i]) {
+                hipFree(kv.second.slot[i]);
+                kv.second.slot[i] = nullptr;
+                kv.second.bytes[i] = 0;
+            }
+    c->ws.clear();
+    return LC_OK;
+}
+
 int lc_ctx_device_bytes(const lc_ctx *x, size_t *bytes)
 {
     if (!x || !bytes) return LC_EINVAL;
-    size_t b = x->c.table_bytes + x->c.key_bytes;
+    size_t b = x->c.table_bytes + x->c.key_bytes + x->c.retired_bytes;
     for (auto &kv : x->c.ws)
         for (int i = 0; i < 8; i++) b += kv.second.bytes[i];
     *bytes = b;
@@ -575,6 +597,38 @@ int lc_masked_sum(lc_ctx *x, const uint64_t *cts, int n, int len, const uint64_t
     return launch_masked_sum(c, cts, n, len, masks, out, (hipStream_t)stream);
 }
 
+int lc_mask_aggregate(lc_ctx *x, const uint64_t *cts, int n, int len, const uint64_t *mask_cts, uint64_t *out,
+                      void *stream)
+{
+    CHECK_CTX(x);
+    if (n < 1 || n > 4096 || len < 1) return fail(c, LC_EINVAL, "need 1 <= n <= 4096 and len >= 1");
+    if (!cts || !mask_cts || !out) return fail(c, LC_EINVAL, "null buffer");
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    const u64 S = (u64)c->nq * c->N;
+    if (overlap(cts, (u64)n * len * 2 * S * 8, out, (u64)len * 2 * S * 8) ||
+        overlap(mask_cts, (u64)n * 2 * S * 8, out, (u64)len * 2 * S * 8))
+        return fail(c, LC_EINVAL, "out must not overlap the inputs");
+    hipStream_t s = (hipStream_t)stream;
+    // triples of a chunk of packed ciphertexts, then one relinearization each
+    const int chunk = std::min(len, std::max(1, c->tune.ks_chunk));
+    u64 *trip = ws_get(c, WS_PIPE, (u64)chunk * 3 * S * 8, s);
+    if (!trip) return LC_ENOMEM;
+    for (int k0 = 0; k0 < len; k0 += chunk) {
+        const int kc = std::min(chunk, len - k0);
+        int rc = launch_mask_mul_acc(c, cts + (u64)k0 * 2 * S, n, kc, len, mask_cts, trip, s);
+        if (rc) return rc;
+        KsGroup g{};
+        g.keys[0] = c->rlk;
+        g.n = 1;
+        g.base = trip;
+        g.base_stride = 3 * S;
+        g.out = out + (u64)k0 * 2 * S;
+        g.out_stride = 2 * S;
+        if ((rc = keyswitch_hoisted(c, trip + 2 * S, 3 * S, kc, &g, 1, s))) return rc;
+    }
+    return LC_OK;
+}
+
 int lc_pair_triples(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t *triples, void *stream)
 {
     CHECK_CTX(x);
@@ -699,6 +753,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cycle") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle: 0/1");
         c->tune.mac_cycle = value;
+    } else if (k == "fuse_modup") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "fuse_modup: 0/1");
+        c->tune.fuse_modup = value;
     } else if (k == "mac_cycle_min") {
         if (value < 1) return fail(c, LC_EINVAL, "mac_cycle_min: >= 1");
         c->tune.mac_cycle_min = value;

@@ -389,12 +389,25 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
         hipLaunchKernelGGL(strided_copy_kernel, dim3(blocks_for(words * B)), dim3(KS_THREADS), 0, s, xb, x_stride,
                            xhat, words, words, B);
         LC_HIP(c, hipGetLastError());
-        if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
-        const u32 tpb = (u32)std::min<u64>(N, KS_THREADS);
-        hipLaunchKernelGGL(modup_bconv_kernel, dim3((u32)(N / tpb), (u32)(B * dnum)), dim3(tpb), 0, s, c->dp, xhat,
-                           raised);
-        LC_HIP(c, hipGetLastError());
-        if ((rc = launch_ntt_fwd(c, PolyBatch{raised, B * dnum, ne, (u64)ne, 0, 1}, s))) return rc;
+        if (c->tune.fuse_modup && c->log_n >= 10) {
+            // the inverse transform's last pass scales limb a by N^-1 (Q_d/q_a)^-1,
+            // leaving the ModUp digits y_a; the forward transform of the raised
+            // limbs computes their base conversion in its first pass
+            PolyBatch ib{xhat, B, nq, (u64)nq, 0, 0};
+            ib.iscale = c->dp.up_scale;
+            if ((rc = launch_ntt_inv(c, ib, s))) return rc;
+            PolyBatch fb{raised, B * dnum, ne, (u64)ne, 0, 1};
+            fb.modup_y = xhat;
+            fb.modup_y_stride = (u64)nq * N;
+            if ((rc = launch_ntt_fwd(c, fb, s))) return rc;
+        } else {
+            if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
+            const u32 tpb = (u32)std::min<u64>(N, KS_THREADS);
+            hipLaunchKernelGGL(modup_bconv_kernel, dim3((u32)(N / tpb), (u32)(B * dnum)), dim3(tpb), 0, s, c->dp,
+                               xhat, raised);
+            LC_HIP(c, hipGetLastError());
+            if ((rc = launch_ntt_fwd(c, PolyBatch{raised, B * dnum, ne, (u64)ne, 0, 1}, s))) return rc;
+        }
         for (int g = 0; g < ngroups; g++) {
             const KsGroup &G = groups[g];
             KeySet ks{};

@@ -31,6 +31,7 @@ struct DevParams {
     const u64 *up_fac;              // [dnum][alpha][ne]: (Q_d / q_a) mod m_l
     const u64 *dn_inv, *dn_inv_sh;  // [np]: (P / p_k)^-1 mod p_k
     const u64 *dn_fac;              // [np][nq]: (P / p_k) mod q_l
+    const u64 *up_scale;            // [nq]: N^-1 (Q_d / q_a)^-1 mod q_a for limb a of digit d
     const double *up_inv_d, *up_fac_d, *dn_inv_d, *dn_fac_d;  // the four tables above as doubles
     const u64 *pinv, *pinv_sh;      // [nq]: P^-1 mod q_l
     const u64 *pmod;                // [nq]: P mod q_l (gadget)
@@ -92,6 +93,8 @@ struct Ctx {
         size_t bytes[8] = {};
     };
     std::map<hipStream_t, Workspace> ws;
+    std::vector<void *> retired;  // outgrown workspace buffers, freed with the context
+    size_t retired_bytes = 0;
     std::map<u64, CycleTable> cycles;  // by Galois element
     size_t ws_limit = 0;
 
@@ -104,6 +107,7 @@ struct Ctx {
         int mac_cts = 8;      // ciphertexts per lane of the key-switch inner product (8 or 16)
         int mac_cycle = 1;    // hoisted blocks of 3 or 7 keys use the cycle-walking inner product ...
         int mac_cycle_min = 16;  // ... when the tile cycles are at least this long
+        int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
 };
@@ -150,6 +154,14 @@ struct PolyBatch {
     u64 gstride;   // in polynomials
     int limb0;
     int skip_own_digit;
+    // inverse only: per-limb scale of the last pass (by absolute limb; NULL = N^-1)
+    const u64 *iscale = nullptr;
+    // forward only, groups = (ciphertext, digit) of raised limbs: the first
+    // pass computes its input as the ModUp base conversion of the digit's
+    // limbs of modup_y ([count / dnum][nq][N], already scaled by
+    // (Q_d / q_a)^-1, canonical) instead of reading base
+    const u64 *modup_y = nullptr;
+    u64 modup_y_stride = 0;  // words per ciphertext
 };
 int launch_ntt_fwd(Ctx *c, const PolyBatch &b, hipStream_t s);
 int launch_ntt_inv(Ctx *c, const PolyBatch &b, hipStream_t s);
@@ -159,6 +171,10 @@ int launch_add_sub(Ctx *c, const u64 *a, const u64 *b, u64 *out, u64 count, int 
 int launch_tensor(Ctx *c, const u64 *a, const u64 *b, u64 *out3, u64 count, hipStream_t s);  // b NULL: square
 int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, hipStream_t s);
 int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s);
+// trip[k] = sum_i cts[i][k] (x) masks[i] for k < len; client i's row starts
+// at cts + i row_len 2 S (row_len >= len packed ciphertexts)
+int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, const u64 *masks, u64 *trip,
+                        hipStream_t s);
 int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
                         int accumulate, hipStream_t s);
 int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s);

@@ -168,7 +168,7 @@ __device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 
 
 // first_: the pass reads uint64 residues (else doubles left by the other pass);
 // final_: the pass writes canonical uint64 residues (times N^-1 when inverse).
-template <int LOG_S, bool INVERSE, bool BLOCKS>
+template <int LOG_S, bool INVERSE, bool BLOCKS, bool FUSED_MODUP = false>
 __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
 {
     constexpr u32 S = 1u << LOG_S;
@@ -195,16 +195,49 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
     }
     // coalesced load into LDS: every lane issues its eight 16-byte loads
     // (element pairs e, e+1 with e even) before writing any of them
-    u64 v[16];
+    double v[16];
+    if (FUSED_MODUP) {  // forward, first pass, raised digits
+        // the raised limb's input is the ModUp base conversion of its digit:
+        // sum_a y_a (Q_d / q_a) mod m over the digit's limbs a of modup_y,
+        // where y_a is already [x^_a (Q_d / q_a)^-1]_{q_a}; the sum (|s| <= 7 m)
+        // is reduced to |s| <= m / 2 + 1, a valid input of the transform
+        const u64 grp = blockIdx.x / (u32)pb.nlimb;
+        const int d = (int)(grp % (u64)dp.dnum);
+        const int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
+        const u64 *yb = pb.modup_y + (grp / (u64)dp.dnum) * pb.modup_y_stride + (u64)a0 * dp.N;
+        const double *fac = dp.up_fac_d + (u64)d * dp.alpha * dp.ne + mi;
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        u32 e = 2 * (tid + (u32)i * nthreads);
-        u64 g;
-        if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
-        else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
-        ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(poly + g);
-        v[2 * i] = p2.x;
-        v[2 * i + 1] = p2.y;
+        for (int i = 0; i < 16; i++) v[i] = 0.0;
+        for (int a = 0; a < na; a++) {
+            const double f = fac[(u64)a * dp.ne];
+            ulonglong2 y2[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                u32 e = 2 * (tid + (u32)i * nthreads);
+                u64 g;
+                if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
+                else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
+                y2[i] = *reinterpret_cast<const ulonglong2 *>(yb + (u64)a * dp.N + g);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                v[2 * i] += mulmod_d(u64_to_d(y2[i].x), f, q, qinv);
+                v[2 * i + 1] += mulmod_d(u64_to_d(y2[i].y), f, q, qinv);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++) v[i] = reduce_d(v[i], q, qinv);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            u32 e = 2 * (tid + (u32)i * nthreads);
+            u64 g;
+            if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
+            else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
+            ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(poly + g);
+            v[2 * i] = first_ ? u64_to_d(p2.x) : __longlong_as_double((long long)p2.x);
+            v[2 * i + 1] = first_ ? u64_to_d(p2.y) : __longlong_as_double((long long)p2.y);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 8; i++) {
@@ -214,8 +247,8 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         else { a = e / (u32)cols; c = e % (u32)cols; }
         // BLOCKS: (c, a), (c, a+1); columns: (c, a), (c+1, a)
         u32 i0 = lds_idx<LOG_S>(c, a), i1 = BLOCKS ? lds_idx<LOG_S>(c, a + 1) : lds_idx<LOG_S>(c + 1, a);
-        lds[i0] = first_ ? u64_to_d(v[2 * i]) : __longlong_as_double((long long)v[2 * i]);
-        lds[i1] = first_ ? u64_to_d(v[2 * i + 1]) : __longlong_as_double((long long)v[2 * i + 1]);
+        lds[i0] = v[2 * i];
+        lds[i1] = v[2 * i + 1];
     }
     __syncthreads();
     const u32 c = tid / TPC, t = tid % TPC;
@@ -237,7 +270,7 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         }
         __syncthreads();
     }
-    const double ni = (double)dp.ninv[mi];
+    const double ni = (double)(pb.iscale ? pb.iscale[mi] : dp.ninv[mi]);
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         u32 e = 2 * (tid + (u32)i * nthreads);
@@ -279,15 +312,15 @@ static int plan_fast(int log_n, FastPass *p)
     return 2;
 }
 
-template <bool INV, bool BLOCKS>
+template <bool INV, bool BLOCKS, bool FUSED = false>
 static void launch_fast_one(int log_s, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &dp,
                             const PolyBatch &b, int s0, int cols, int final_)
 {
     switch (log_s) {
-    case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     }
 }
 
@@ -318,6 +351,8 @@ static int launch_fast(Ctx *c, const PolyBatch &b, const FastPass *fp, hipStream
         if (inverse) {
             if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
             else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        } else if (k == 0 && b.modup_y) {  // first forward pass (columns) with the ModUp conversion
+            launch_fast_one<false, false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
         } else {
             if (P.blocks) launch_fast_one<false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
             else launch_fast_one<false, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
@@ -348,11 +383,13 @@ static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
             PolyBatch sb = b;
             sb.base = b.base + g0 * b.gstride * c->N;
             sb.count = std::min(gsub, b.count - g0);
+            if (b.modup_y) sb.modup_y = b.modup_y + (g0 / (u64)c->dnum) * b.modup_y_stride;  // g0 % dnum == 0
             int rc = launch_fast(c, sb, fp, s, inverse);
             if (rc) return rc;
         }
         return LC_OK;
     }
+    if (b.modup_y) return fail(c, LC_EINVAL, "the fused ModUp transform needs 2^10 <= N <= 2^16");
     PassArgs pass[2];
     int np = plan_passes(c->log_n, pass);
     for (int k = 0; k < np; k++) {

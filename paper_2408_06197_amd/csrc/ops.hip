@@ -170,6 +170,85 @@ int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, 
     return LC_OK;
 }
 
+// ---- ServerUpdate with an encrypted mask --------------------------------------
+//
+// trip[k] = sum_i ct_i[k] (x) mask_i: the tensor product (a0 m0, a0 m1 + a1 m0,
+// a1 m1) of every client's packed ciphertext with that client's encrypted
+// mask (Enc_pk of its weight), summed over clients before one
+// relinearization per k.  Same structure as the masked sum: a lane owns one
+// coefficient and MA_ROWS packed ciphertexts, clients go in pairs whose mask
+// components sit in registers, every client ciphertext is read once.  FP64
+// Barrett products below q (|r| < q), a reduction after every 4 products per
+// accumulator.
+constexpr int MA_TILE = 256;
+constexpr int MA_ROWS = 8;
+
+__global__ void __launch_bounds__(MA_TILE)
+mask_mul_acc_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int row_len,
+                    const u64 *__restrict__ masks, u64 *__restrict__ trip)
+{
+    const u64 S = (u64)dp.nq << dp.log_n;
+    const u64 r = (u64)blockIdx.x * MA_TILE + threadIdx.x;  // (limb, coefficient)
+    if (r >= S) return;
+    const int k0 = blockIdx.y * MA_ROWS;
+    const int l = (int)(r >> dp.log_n);
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+    const u64 client_stride = (u64)row_len * 2 * S;  // a client's row holds row_len ciphertexts, of which len are used
+    double acc[MA_ROWS][3];
+#pragma unroll
+    for (int t = 0; t < MA_ROWS; t++) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 2) {
+        double m[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const bool live = i0 + u < n;
+            m[u][0] = live ? u64_to_d(masks[(u64)(i0 + u) * 2 * S + r]) : 0.0;
+            m[u][1] = live ? u64_to_d(masks[(u64)(i0 + u) * 2 * S + S + r]) : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < MA_ROWS; t++) {
+            if (k0 + t < len) {
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    double a0 = 0.0, a1 = 0.0;
+                    if (i0 + u < n) {
+                        const u64 *c = cts + (u64)(i0 + u) * client_stride + (u64)(k0 + t) * 2 * S + r;
+                        a0 = u64_to_d(c[0]);
+                        a1 = u64_to_d(c[S]);
+                    }
+                    acc[t][0] += mulmod_d(a0, m[u][0], q, qinv);
+                    acc[t][1] += mulmod_d(a0, m[u][1], q, qinv) + mulmod_d(a1, m[u][0], q, qinv);
+                    acc[t][2] += mulmod_d(a1, m[u][1], q, qinv);
+                }
+                acc[t][0] = reduce_d(acc[t][0], q, qinv);
+                acc[t][1] = reduce_d(acc[t][1], q, qinv);
+                acc[t][2] = reduce_d(acc[t][2], q, qinv);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < MA_ROWS; t++) {
+        if (k0 + t < len) {
+            u64 *o = trip + (u64)(k0 + t) * 3 * S + r;
+            o[0] = d_to_canonical(acc[t][0], q, qinv);
+            o[S] = d_to_canonical(acc[t][1], q, qinv);
+            o[2 * S] = d_to_canonical(acc[t][2], q, qinv);
+        }
+    }
+}
+
+int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, const u64 *masks, u64 *trip,
+                        hipStream_t s)
+{
+    const u64 S = (u64)c->nq * c->N;
+    if (len < 1 || n < 1) return LC_OK;
+    if (len > row_len) return fail(c, LC_EINVAL, "chunk longer than the client row");
+    dim3 grid((u32)((S + MA_TILE - 1) / MA_TILE), (u32)((len + MA_ROWS - 1) / MA_ROWS));
+    hipLaunchKernelGGL(mask_mul_acc_kernel, grid, dim3(MA_TILE), 0, s, c->dp, cts, n, len, row_len, masks, trip);
+    LC_HIP(c, hipGetLastError());
+    return LC_OK;
+}
+
 // ---- fused subtract / square / lazy accumulate over all pairs --------------
 //
 // Workgroup = (tile of T coefficients, limb l, chunk of pairs).  PT_KB packed

@@ -65,6 +65,8 @@ _SIGS = {
     "lc_rotate_sum": [VP, VP, SZ, PINT, INT, VP],
     "lc_mul_plain": [VP, VP, VP, VP, SZ, VP],
     "lc_masked_sum": [VP, VP, INT, INT, VP, VP, VP],
+    "lc_mask_aggregate": [VP, VP, INT, INT, VP, VP, VP],
+    "lc_release_workspace": [VP],
     "lc_pair_triples": [VP, VP, INT, INT, VP, VP],
     "lc_pair_triples_acc": [VP, VP, INT, INT, VP, VP],
     "lc_pairwise_finish": [VP, VP, INT, PINT, INT, VP, VP, VP],
@@ -310,6 +312,13 @@ class Context:
         self._check(lib().lc_masked_sum(self._h, _ptr(cts), n, ln, _ptr(masks), _ptr(out), _stream(stream)))
         return out
 
+    def mask_aggregate(self, cts, mask_cts, out=None, stream=None):
+        """sum_i cts[i][k] (x) mask_cts[i], relinearized: [len][2][n_q][N]."""
+        n, ln = cts.shape[0], cts.shape[1]
+        out = self.empty(ln, 2, self.nq, self.N) if out is None else out
+        self._check(lib().lc_mask_aggregate(self._h, _ptr(cts), n, ln, _ptr(mask_cts), _ptr(out), _stream(stream)))
+        return out
+
     def pair_triples(self, cts, out=None, stream=None):
         n, ln = cts.shape[0], cts.shape[1]
         P = n * (n - 1) // 2
@@ -363,6 +372,9 @@ class Context:
         b = SZ()
         self._check(lib().lc_workspace_query(self._h, n, len_, _c.byref(b)))
         return b.value
+
+    def release_workspace(self):
+        self._check(lib().lc_release_workspace(self._h))
 
     def set_tuning(self, name, value):
         self._check(lib().lc_set_tuning(self._h, name.encode(), int(value)))

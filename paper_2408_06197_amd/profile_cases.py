@@ -2,6 +2,7 @@
 
     python -m paper_2408_06197_amd.profile_cases pair       # one pair-triple launch
     python -m paper_2408_06197_amd.profile_cases keyswitch  # one rotate-and-sum of 16 ciphertexts
+    python -m paper_2408_06197_amd.profile_cases keyswitch fuse_modup=0   # with lc_set_tuning overrides
 
 Both run at N = 2^16 with 24 + 4 limbs of 50 bits on random residues, then
 copy 4 GiB with a plain device copy so that each counter can be scaled by
@@ -26,9 +27,11 @@ def _calibration_copy():
     torch.cuda.synchronize()
 
 
-def pair(lanes=16, ppt=6, n=20, ln=342):
+def pair(tune, lanes=16, ppt=6, n=20, ln=342):
     """lc_pair_triples over 20 clients x 342 packed ciphertexts (172 GB)."""
     ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
+    for k, v in tune.items():
+        ctx.set_tuning(k, v)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
     cts = torch.empty((n, ln, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
@@ -43,12 +46,14 @@ def pair(lanes=16, ppt=6, n=20, ln=342):
     _calibration_copy()
 
 
-def keyswitch(count=16, plan=(3, 3, 3, 3, 3)):
+def keyswitch(tune, count=16, plan=(3, 3, 3, 3, 3)):
     """lc_rotate_sum of `count` ciphertexts with the given hoisting plan."""
     ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
     ctx.keygen(7)
     ctx.keygen_rotation(7, ctx.rotsum_steps(list(plan)))
     ctx.set_tuning("ks_chunk", count)
+    for k, v in tune.items():
+        ctx.set_tuning(k, v)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
     ct = torch.empty((count, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
@@ -62,6 +67,7 @@ if __name__ == "__main__":
     case = sys.argv[1] if len(sys.argv) > 1 else "pair"
     if case not in ("pair", "keyswitch"):
         sys.exit("cases: pair, keyswitch")
+    tune = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in sys.argv[2:])
     torch.cuda.set_device(0)
-    {"pair": pair, "keyswitch": keyswitch}[case]()
+    {"pair": pair, "keyswitch": keyswitch}[case](tune)
     print(f"profile case {case} done", flush=True)

@@ -105,6 +105,7 @@ class Scheduler:
         self.slots = slots
         self.k_chunk = k_chunk
         self.used = 0
+        self.deferred = 0  # admissions the executor put off for lack of device memory
         self.active: Dict[int, tuple] = {}
 
     def footprint(self, spec: RoundSpec) -> int:
@@ -117,9 +118,11 @@ class Scheduler:
         return len(self.active) < self.slots and self.used + fp <= self.budget
 
     def run(self, specs: List[RoundSpec], executor, clock: Callable[[], float] = time.perf_counter,
-            sleep: Callable[[float], None] = time.sleep) -> Dict[int, dict]:
+            sleep: Callable[[float], None] = time.sleep,
+            on_done: Callable[[int, dict], None] = None) -> Dict[int, dict]:
         """Serve `specs` (sorted by arrival).  Returns per-round records with
-        arrival, admit and completion times (seconds from the start)."""
+        arrival, admit and completion times (seconds from the start);
+        on_done(rounds_finished, record) is called as each round completes."""
         pending = sorted(specs, key=lambda s: s.arrival)
         waiting: List[RoundSpec] = []
         done: Dict[int, dict] = {}
@@ -130,12 +133,23 @@ class Scheduler:
             while i < len(pending) and pending[i].arrival <= now:
                 waiting.append(pending[i])
                 i += 1
-            # admit in arrival order while capacity allows
+            # admit in arrival order while capacity allows; an executor that
+            # cannot place a round right now (start returns None) keeps it at
+            # the head of the queue until a running round frees memory
             while waiting and self.can_admit(waiting[0]):
-                spec = waiting.pop(0)
+                spec = waiting[0]
+                handle = executor.start(spec)
+                if handle is None:
+                    if not self.active:
+                        raise MemoryError("round %d (n=%d, dim=%d, %s; footprint %d bytes) cannot be placed even "
+                                          "on an idle device: %s" % (spec.rid, spec.n, spec.dim, spec.chain,
+                                                                     self.footprint(spec),
+                                                                     getattr(executor, "last_refusal", None)))
+                    self.deferred += 1
+                    break
+                waiting.pop(0)
                 fp = self.footprint(spec)
                 self.used += fp
-                handle = executor.start(spec)
                 self.active[spec.rid] = (spec, handle, fp, clock() - t0)
             progressed = False
             for rid in list(self.active):
@@ -149,6 +163,8 @@ class Scheduler:
                                  "latency": t_done - spec.arrival, "chain": spec.chain, "n": spec.n, "dim": spec.dim,
                                  "result": result}
                     progressed = True
+                    if on_done is not None:
+                        on_done(len(done), done[rid])
             if not progressed:
                 nxt = pending[i].arrival - (clock() - t0) if i < len(pending) else None
                 if self.active or waiting:
@@ -227,7 +243,8 @@ class GpuExecutor:
     """Runs each admitted round on a stream of its own through the C ABI."""
 
     def __init__(self, torch, contexts: Dict[str, tuple], pools: Dict[str, PlaintextPool],
-                 chains: Dict[str, ChainInfo], plans: Dict[str, list], k_chunk: int, streams: int):
+                 chains: Dict[str, ChainInfo], plans: Dict[str, list], k_chunk: int, streams: int,
+                 keep_ciphertexts: bool = False):
         self.torch = torch
         self.contexts = contexts        # chain -> (kgc ctx, server ctx)
         self.pools = pools
@@ -236,6 +253,11 @@ class GpuExecutor:
         self.k_chunk = k_chunk
         self.free_streams = [torch.cuda.Stream() for _ in range(streams)]
         self.pending = {}
+        self.last_refusal = None
+        # a finished round's result holds its distance ciphertexts on the
+        # device only when asked (tests compare them); otherwise its memory
+        # goes back to the pool as soon as the KGC's read-out is done
+        self.keep_ciphertexts = keep_ciphertexts
 
     def _plaintexts(self, spec, pool, ch, k0, k):
         """[n][k][N] encoded plaintexts of chunk k0..k0+k of every client."""
@@ -264,14 +286,23 @@ class GpuExecutor:
         return torch.stack(rows).contiguous()
 
     def start(self, spec: RoundSpec):
-        try:
-            return self._start(spec)
-        except Exception as e:  # device memory pressure: release torch's cache once and retry
-            if "allocation" not in str(e) and "out of memory" not in str(e):
-                raise
-            self.torch.cuda.synchronize()
-            self.torch.cuda.empty_cache()
-            return self._start(spec)
+        """Enqueue a round; None if the device cannot hold it right now (the
+        scheduler retries once a running round has finished)."""
+        for attempt in range(2):
+            try:
+                return self._start(spec)
+            except Exception as e:  # device memory pressure
+                if "allocation" not in str(e) and "out of memory" not in str(e):
+                    raise
+                free, total = self.torch.cuda.mem_get_info()
+                self.last_refusal = ("%s | device free %.1f of %.1f GiB, torch allocated %.1f GiB, reserved %.1f GiB"
+                                     % (str(e).splitlines()[0][:200], free / 2 ** 30, total / 2 ** 30,
+                                        self.torch.cuda.memory_allocated() / 2 ** 30,
+                                        self.torch.cuda.memory_reserved() / 2 ** 30))
+                if attempt == 0:  # release torch's cached blocks of finished rounds and retry once
+                    self.torch.cuda.synchronize()
+                    self.torch.cuda.empty_cache()
+        return None
 
     def _start(self, spec: RoundSpec):
         stream = self.free_streams.pop()
@@ -314,4 +345,8 @@ class GpuExecutor:
         c0 = h["coeff0"].cpu().numpy().view(np.uint64).T.copy()
         d = kgc.crt_to_double(c0) / 2.0 ** (2 * ch.scale_log2)
         self.free_streams.append(h["stream"])
-        return {"distances": d, "dist_ct": h["dist"]}
+        out = {"distances": d}
+        if self.keep_ciphertexts:
+            out["dist_ct"] = h["dist"]
+        h.clear()
+        return out

@@ -85,6 +85,42 @@ def test_round_larger_than_budget_is_refused():
         sch.can_admit(spec)
 
 
+def test_executor_refusal_defers_round():
+    """A round the executor cannot place (start returns None, as on device
+    memory pressure) stays at the head of the queue and is started after a
+    running round finishes; nothing is lost or reordered."""
+    clock = FakeClock()
+    specs = serve.make_stream(30, rate=100.0, chains=["a"], seed=9, dims=(100_000,))
+    sch = serve.Scheduler(CH, budget_bytes=1 << 62, slots=4, k_chunk=64)
+    ex = FakeExecutor(clock, lambda s: 0.02)
+    orig = ex.start
+    refused = []
+
+    def start(spec):
+        if ex.active >= 2 and spec.rid % 3 == 0 and spec.rid not in refused:
+            refused.append(spec.rid)
+            return None
+        return orig(spec)
+
+    ex.start = start
+    rec = sch.run(specs, ex, clock=clock, sleep=clock.sleep)
+    assert sorted(rec) == list(range(30)) and refused
+    starts = [rid for rid, _ in ex.started]
+    assert starts == sorted(starts)
+    for rid in refused:
+        assert rec[rid]["admit"] > rec[rid]["arrival"]
+
+
+def test_refusal_on_idle_device_raises():
+    clock = FakeClock()
+    specs = serve.make_stream(2, rate=0.0, chains=["a"], seed=1, dims=(100_000,))
+    sch = serve.Scheduler(CH, budget_bytes=1 << 62, slots=2, k_chunk=64)
+    ex = FakeExecutor(clock, lambda s: 0.01)
+    ex.start = lambda spec: None
+    with pytest.raises(MemoryError):
+        sch.run(specs, ex, clock=clock, sleep=clock.sleep)
+
+
 def test_stream_draws():
     specs = serve.make_stream(500, rate=2.0, chains=["a", "b"])
     assert len(specs) == 500
@@ -118,7 +154,8 @@ def test_alone_equals_mix_and_decrypts():
     budget = 1 << 30
 
     def run(sp, slots):
-        ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=2, streams=slots)
+        ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=2, streams=slots,
+                               keep_ciphertexts=True)
         return serve.Scheduler(chains, budget, slots=slots, k_chunk=2).run(sp, ex)
 
     alone = {}
