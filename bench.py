@@ -445,6 +445,15 @@ def main():
         tuned["plan"], tuned["mac_cycle_min"] = plan, bestp[2]
         # key-switch inner-product width and batch, on the chosen plan (the NTT
         # sub-batch knob measured no gain at this size and stays off)
+        bestm = None
+        for shp in (0, 1, 2):  # masked-sum lane shape
+            srv.set_tuning("ms_shape", shp)
+            ms = event_time(torch, lambda: srv.masked_sum(cts, masks, out=agg))
+            tuned.setdefault("ms_shape_ms", {})[str(shp)] = ms
+            if bestm is None or ms < bestm[0]:
+                bestm = (ms, shp)
+        srv.set_tuning("ms_shape", bestm[1])
+        tuned["ms_shape"] = bestm[1]
         for name, values in (("mac_cts", (8, 16)), ("ks_chunk", (32, 64, 128))):
             bestv = None
             for v in values:

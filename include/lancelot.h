@@ -243,7 +243,9 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * inner product that reads each raised digit once; 0 = one gather per key),
  * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used),
  * "fuse_modup" (1 = for 2^10 <= N the ModUp base conversion runs inside the
- * first forward-NTT pass of the raised digits; 0 = a kernel of its own).
+ * first forward-NTT pass of the raised digits; 0 = a kernel of its own),
+ * "ms_shape" (masked-sum lanes: 0 = 1 coefficient x 16 rows, 1 = 2 x 8,
+ * 2 = 2 x 16).
  * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

@@ -753,6 +753,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cycle") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle: 0/1");
         c->tune.mac_cycle = value;
+    } else if (k == "ms_shape") {
+        if (value < 0 || value > 2) return fail(c, LC_EINVAL, "ms_shape: 0/1/2");
+        c->tune.ms_shape = value;
     } else if (k == "fuse_modup") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "fuse_modup: 0/1");
         c->tune.fuse_modup = value;

@@ -108,6 +108,7 @@ struct Ctx {
         int mac_cycle = 1;    // hoisted blocks of 3 or 7 keys use the cycle-walking inner product ...
         int mac_cycle_min = 16;  // ... when the tile cycles are at least this long
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
+        int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
 };

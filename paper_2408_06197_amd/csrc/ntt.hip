@@ -177,7 +177,15 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
     extern __shared__ double lds[];
     u64 *poly;
     int mi;
-    if (!poly_of_block(dp, pb, blockIdx.x, poly, mi)) return;
+    u64 pidx = blockIdx.x;
+    if (FUSED_MODUP && (pb.count & 7) == 0) {
+        // workgroups are dealt to the 8 XCDs round-robin: remap so that the
+        // limbs of one (ciphertext, digit) group run on one XCD and share its
+        // L2 copy of the group's ModUp digits
+        const u64 j = blockIdx.x >> 3, nl = (u64)pb.nlimb;
+        pidx = ((j / nl) * 8 + (blockIdx.x & 7)) * nl + j % nl;
+    }
+    if (!poly_of_block(dp, pb, pidx, poly, mi)) return;
     const double q = dp.mc[mi].qd, qinv = dp.mc[mi].qinv;
     const u32 tile = blockIdx.y;
     const u32 stride = dp.N >> (s0 + LOG_S);
@@ -201,7 +209,7 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         // sum_a y_a (Q_d / q_a) mod m over the digit's limbs a of modup_y,
         // where y_a is already [x^_a (Q_d / q_a)^-1]_{q_a}; the sum (|s| <= 7 m)
         // is reduced to |s| <= m / 2 + 1, a valid input of the transform
-        const u64 grp = blockIdx.x / (u32)pb.nlimb;
+        const u64 grp = pidx / (u64)pb.nlimb;
         const int d = (int)(grp % (u64)dp.dnum);
         const int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
         const u64 *yb = pb.modup_y + (grp / (u64)dp.dnum) * pb.modup_y_stride + (u64)a0 * dp.N;

@@ -111,61 +111,107 @@ int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, 
 
 // out[k][comp][l][j] = sum_i cts[i][k][comp][l][j] * masks[i][l][j]
 //
-// Workgroup = (256 consecutive coefficients of one (limb, position) range,
-// MS_ROWS consecutive (k, comp) rows).  A lane owns one coefficient and the
-// MS_ROWS row accumulators; clients go in groups of 8 whose mask values are
-// loaded once into registers and used for every row, so the masks cost
-// 1 / MS_ROWS of a read per output instead of one (the client ciphertexts
-// are read exactly once).  FP64 Barrett products of residues below q come
-// back with |r| < q; a reduction follows every 4 products, so the
-// accumulators stay below 4.5 q < 2^53.
+// Workgroup = (256 x COEF consecutive coefficients of one (limb, position)
+// range, ROWS consecutive (k, comp) rows).  A lane owns COEF adjacent
+// coefficients (COEF = 2: 16-byte accesses) and their ROWS row accumulators;
+// clients go in groups of 8 whose mask values are loaded once into
+// registers and used for every row, so the masks cost 1 / ROWS of a read
+// per output instead of one (the client ciphertexts are read exactly once).
+// FP64 Barrett products of residues below q come back with |r| < q; a
+// reduction follows every 4 products, so the accumulators stay below
+// 4.5 q < 2^53.  The shape (COEF, ROWS) is a tuning choice ("ms_shape").
 constexpr int MS_TILE = 256;
-constexpr int MS_ROWS = 16;
 
+template <int COEF, int ROWS>
 __global__ void __launch_bounds__(MS_TILE)
 masked_sum_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, const u64 *__restrict__ masks,
                   u64 *__restrict__ out)
 {
     const u64 S = (u64)dp.nq << dp.log_n;
-    const u64 r = (u64)blockIdx.x * MS_TILE + threadIdx.x;  // (limb, coefficient)
+    const u64 r = ((u64)blockIdx.x * MS_TILE + threadIdx.x) * COEF;  // (limb, coefficient), COEF | N
     if (r >= S) return;
-    const int rows = 2 * len, row0 = blockIdx.y * MS_ROWS;
+    const int rows = 2 * len, row0 = blockIdx.y * ROWS;
     const int l = (int)(r >> dp.log_n);
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     const u64 client_stride = (u64)len * 2 * S;
-    double acc[MS_ROWS];
+    double acc[ROWS][COEF];
 #pragma unroll
-    for (int t = 0; t < MS_ROWS; t++) acc[t] = 0.0;
+    for (int t = 0; t < ROWS; t++)
+#pragma unroll
+        for (int e = 0; e < COEF; e++) acc[t][e] = 0.0;
     for (int i0 = 0; i0 < n; i0 += 8) {
-        double m[8];
+        double m[8][COEF];
 #pragma unroll
-        for (int u = 0; u < 8; u++) m[u] = i0 + u < n ? u64_to_d(masks[(u64)(i0 + u) * S + r]) : 0.0;
+        for (int u = 0; u < 8; u++) {
+            if (COEF == 2) {
+                ulonglong2 v = i0 + u < n ? *reinterpret_cast<const ulonglong2 *>(masks + (u64)(i0 + u) * S + r)
+                                          : ulonglong2{0, 0};
+                m[u][0] = u64_to_d(v.x);
+                m[u][COEF - 1] = u64_to_d(v.y);
+            } else {
+                m[u][0] = i0 + u < n ? u64_to_d(masks[(u64)(i0 + u) * S + r]) : 0.0;
+            }
+        }
         const u64 *base = cts + (u64)i0 * client_stride + (u64)row0 * S + r;
 #pragma unroll
-        for (int t = 0; t < MS_ROWS; t++) {
+        for (int t = 0; t < ROWS; t++) {
             if (row0 + t < rows) {
-                double c[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) c[u] = i0 + u < n ? u64_to_d(base[(u64)u * client_stride + (u64)t * S]) : 0.0;
+                double c[8][COEF];
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
-                    acc[t] += mulmod_d(c[u], m[u], q, qinv);
-                    if (u == 3 || u == 7) acc[t] = reduce_d(acc[t], q, qinv);
+                    const u64 *src = base + (u64)u * client_stride + (u64)t * S;
+                    if (COEF == 2) {
+                        ulonglong2 v = i0 + u < n ? *reinterpret_cast<const ulonglong2 *>(src) : ulonglong2{0, 0};
+                        c[u][0] = u64_to_d(v.x);
+                        c[u][COEF - 1] = u64_to_d(v.y);
+                    } else {
+                        c[u][0] = i0 + u < n ? u64_to_d(*src) : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+#pragma unroll
+                    for (int e = 0; e < COEF; e++) {
+                        acc[t][e] += mulmod_d(c[u][e], m[u][e], q, qinv);
+                        if (u == 3 || u == 7) acc[t][e] = reduce_d(acc[t][e], q, qinv);
+                    }
                 }
             }
         }
     }
 #pragma unroll
-    for (int t = 0; t < MS_ROWS; t++)
-        if (row0 + t < rows) out[(u64)(row0 + t) * S + r] = d_to_canonical(acc[t], q, qinv);
+    for (int t = 0; t < ROWS; t++) {
+        if (row0 + t < rows) {
+            u64 *o = out + (u64)(row0 + t) * S + r;
+            if (COEF == 2) {
+                ulonglong2 v;
+                v.x = d_to_canonical(acc[t][0], q, qinv);
+                v.y = d_to_canonical(acc[t][COEF - 1], q, qinv);
+                *reinterpret_cast<ulonglong2 *>(o) = v;
+            } else {
+                *o = d_to_canonical(acc[t][0], q, qinv);
+            }
+        }
+    }
+}
+
+template <int COEF, int ROWS>
+static void launch_ms(hipStream_t s, const DevParams &dp, u64 S, const u64 *cts, int n, int len, const u64 *masks,
+                      u64 *out)
+{
+    dim3 grid((u32)((S / COEF + MS_TILE - 1) / MS_TILE), (u32)((2 * len + ROWS - 1) / ROWS));
+    hipLaunchKernelGGL((masked_sum_kernel<COEF, ROWS>), grid, dim3(MS_TILE), 0, s, dp, cts, n, len, masks, out);
 }
 
 int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, u64 *out, hipStream_t s)
 {
     const u64 S = (u64)c->nq * c->N;
     if (len < 1 || n < 1) return LC_OK;
-    dim3 grid((u32)((S + MS_TILE - 1) / MS_TILE), (u32)((2 * len + MS_ROWS - 1) / MS_ROWS));
-    hipLaunchKernelGGL(masked_sum_kernel, grid, dim3(MS_TILE), 0, s, c->dp, cts, n, len, masks, out);
+    switch (c->tune.ms_shape) {  // COEF x ROWS
+    case 0: launch_ms<1, 16>(s, c->dp, S, cts, n, len, masks, out); break;
+    case 1: launch_ms<2, 8>(s, c->dp, S, cts, n, len, masks, out); break;
+    default: launch_ms<2, 16>(s, c->dp, S, cts, n, len, masks, out); break;
+    }
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }

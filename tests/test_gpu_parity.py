@@ -210,8 +210,9 @@ def test_elementwise_bitexact(torch, L, oracle_mod, prm):
     assert np.array_equal(ms, ora.masked_sum(client_cts, masks))
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("log_n,n,ln", [(6, 11, 9), (9, 8, 8), (12, 17, 3)])
-def test_masked_sum_shapes_bitexact(torch, L, oracle_mod, log_n, n, ln):
+def test_masked_sum_shapes_bitexact(torch, L, oracle_mod, log_n, n, ln, shape):
     """Masked aggregation with full-range masks: client groups of 8 with a
     ragged last group, (k, comp) row blocks with a ragged last block, and a
     limb-coefficient range that ends inside a workgroup (N = 2^6)."""
@@ -221,6 +222,7 @@ def test_masked_sum_shapes_bitexact(torch, L, oracle_mod, log_n, n, ln):
     ora = O.Oracle(*prm)
     cts = synth.uniform_residues(300 + n, ctx.q, (n, ln, 2, ctx.N))
     masks = synth.uniform_residues(400 + n, ctx.q, (n, ctx.N))
+    ctx.set_tuning("ms_shape", shape)
     got = down(ctx.masked_sum(up(torch, cts), up(torch, masks)))
     assert np.array_equal(got, ora.masked_sum(cts, masks))
 
@@ -481,7 +483,7 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
 def test_set_tuning_rejects_bad_values(L):
     ctx = L.Context(5, (30, 28, 28), (30,), device=0)
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
-                        ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("nope", 1)):
+                        ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
