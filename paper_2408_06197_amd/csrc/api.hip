@@ -753,6 +753,12 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cycle") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle: 0/1");
         c->tune.mac_cycle = value;
+    } else if (k == "mac_cycle_cts") {
+        if (value != 8 && value != 16) return fail(c, LC_EINVAL, "mac_cycle_cts: 8/16");
+        c->tune.mac_cycle_cts = value;
+    } else if (k == "mac_cycle_c0") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle_c0: 0/1");
+        c->tune.mac_cycle_c0 = value;
     } else if (k == "ms_shape") {
         if (value < 0 || value > 2) return fail(c, LC_EINVAL, "ms_shape: 0/1/2");
         c->tune.ms_shape = value;

@@ -140,46 +140,53 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
 // reads source tile tau^t(o).  Walking a cycle c_0, c_1 = tau(c_0), ... of
 // tau, output c_m reads c_{m+1} .. c_{m+R}, so a workgroup that walks the
 // cycle needs one new source tile per step: it stages source tile c_p (all
-// digits of MAC_CB ciphertexts, as doubles) and the keys of the R outputs
+// digits of 8 or 16 ciphertexts, as doubles) and the keys of the R outputs
 // that read it (c_{p-1} with key 1 ... c_{p-R} with key R) in LDS, adds the
 // contributions, and writes c_{p-R}, which is then complete.  Accumulators
 // live in registers by age.  The raised digits are read about
 // (1 + (R - 1) / KS_CYC_SEG) times instead of R times, every key value once
-// per MAC_CB ciphertexts.  Short cycles re-stage the same tiles, which the
+// per 8 or 16 ciphertexts.  Short cycles re-stage the same tiles, which the
 // caches serve.  Same FP64 Barrett products and reductions as mac_kernel
 // (a reduction after every 4 products), so the same residues.
-constexpr int MAC_CB = 8;  // ciphertexts per workgroup (one per thread row)
-
-template <int R, int D>
-__global__ void __launch_bounds__(KS_CYC_TILE * MAC_CB, 3)
-mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, const CycleSeg *segs,
-                 const u32 *walk, u64 *acc, u64 count)
+// With c0 given, the block's sum_t phi_t(c0) rides along: its tiles are the
+// same source tiles, so it is staged with the digits and added to the Q
+// limbs of accumulator 0 times P mod q (exact after ModDown, which divides
+// by P), and the combine kernel skips its per-key gathers of c0.
+template <int R, int D, int CB, bool FOLD>
+__global__ void __launch_bounds__(KS_CYC_TILE * CB, CB == 8 ? (FOLD ? 2 : 3) : 1)
+mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
+                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count)
 {
     constexpr int TT = KS_CYC_TILE;
-    __shared__ double xt[MAC_CB * D * TT];  // [MAC_CB][D][TT]: source tile c_p
-    __shared__ double kt[R * 2 * D * TT];   // [R][2 D][TT]: keys of the outputs c_{p-1} .. c_{p-R}
+    constexpr int XD = FOLD ? D + 1 : D;     // staged rows per ciphertext: D digits (and c0)
+    __shared__ double xt[CB * XD * TT];      // [CB][XD][TT]: source tile c_p
+    __shared__ double kt[R * 2 * D * TT];    // [R][2 D][TT]: keys of the outputs c_{p-1} .. c_{p-R}
     const int u = threadIdx.x, bl = threadIdx.y;
     const CycleSeg sg = segs[blockIdx.x];
     const int l = blockIdx.y;
-    const u64 b = (u64)blockIdx.z * MAC_CB + bl;
+    const u64 b = (u64)blockIdx.z * CB + bl;
     const bool live = b < count;
     const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     const int own = l < dp.nq ? l / dp.alpha : -1;
+    const bool fold = FOLD && l < dp.nq;
+    const double pq = fold ? u64_to_d(dp.pmod[l]) : 0.0;
 
-    // Staging roles: thread row bl stages its ciphertext's D digit values at
-    // lane u, and (for bl < R) the 2 D key values of key bl + 1 for the
-    // output that key serves at this step.  The loads of step p + 1 are in
-    // flight while step p computes.
+    // Staging roles: thread row bl stages its ciphertext's D digit values
+    // (and c0) at lane u, and (for bl < R) the 2 D key values of key bl + 1
+    // for the output that key serves at this step.  The loads of step p + 1
+    // are in flight while step p computes.
     const u64 *xraised = raised + (b * D * dp.ne + l) * N + u;
     const u64 *xown = x + b * x_stride + lN + u;
+    const u64 *xc0 = fold ? c0 + b * c0_stride + lN + u : nullptr;
     const u64 *ksrc = bl < R ? ks.key[bl] + lN + u : nullptr;
-    u64 xv[D], kv[2 * D];
+    u64 xv[XD], kv[2 * D];
     auto fetch = [&](int p) {
         const u64 src = (u64)walk[sg.base + p % sg.len] * TT;
 #pragma unroll
         for (int d = 0; d < D; d++)
             xv[d] = live ? (d == own ? xown[src] : xraised[(u64)d * dp.ne * N + src]) : 0;
+        if (FOLD) xv[XD - 1] = (live && fold) ? xc0[src] : 0;
         const int m = p - 1 - bl;  // output served by key bl + 1
         const bool kl = bl < R && m >= sg.m0 && m < sg.m0 + sg.cnt;
         const u64 dst = kl ? (u64)walk[sg.base + m % sg.len] * TT : 0;
@@ -188,7 +195,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, Ke
     };
     auto store = [&]() {
 #pragma unroll
-        for (int d = 0; d < D; d++) xt[(bl * D + d) * TT + u] = u64_to_d(xv[d]);
+        for (int d = 0; d < XD; d++) xt[(bl * XD + d) * TT + u] = u64_to_d(xv[d]);
         if (bl < R) {
 #pragma unroll
             for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
@@ -209,7 +216,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, Ke
             const int m = p - t;
             if (m >= sg.m0 && m < sg.m0 + sg.cnt) {
                 const u64 j = (u64)walk[sg.base + m % sg.len] * TT + u;
-                const double *xs = xt + bl * D * TT + (ks.perm[t - 1][j] & (TT - 1));
+                const double *xs = xt + bl * XD * TT + (ks.perm[t - 1][j] & (TT - 1));
                 const double *kk = kt + (t - 1) * 2 * D * TT + u;
                 double a0 = A[t - 1][0], a1 = A[t - 1][1];
 #pragma unroll
@@ -222,6 +229,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, Ke
                         a1 = reduce_d(a1, q, qinv);
                     }
                 }
+                if (FOLD && fold) a0 += mulmod_d(xs[(XD - 1) * TT], pq, q, qinv);
                 A[t - 1][0] = reduce_d(a0, q, qinv);
                 A[t - 1][1] = reduce_d(a1, q, qinv);
             }
@@ -242,18 +250,44 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, Ke
     }
 }
 
-template <int R>
-static void launch_mac_cycle(int dnum, dim3 grid, dim3 block, hipStream_t s, const DevParams &dp, const u64 *x,
-                             u64 x_stride, const u64 *raised, const KeySet &ks, const CycleTable *cyc, u64 *acc,
-                             u64 count)
+template <int R, int CB, bool FOLD>
+static void launch_mac_cycle_cb(int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x, u64 x_stride,
+                                const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
+                                const CycleTable *cyc, u64 *acc, u64 count)
 {
+    dim3 block(KS_CYC_TILE, CB);
     switch (dnum) {
-    case 3: hipLaunchKernelGGL((mac_cycle_kernel<R, 3>), grid, block, 0, s, dp, x, x_stride, raised, ks, cyc->segs,
-                               cyc->walk, acc, count); break;
-    case 4: hipLaunchKernelGGL((mac_cycle_kernel<R, 4>), grid, block, 0, s, dp, x, x_stride, raised, ks, cyc->segs,
-                               cyc->walk, acc, count); break;
-    default: hipLaunchKernelGGL((mac_cycle_kernel<R, 6>), grid, block, 0, s, dp, x, x_stride, raised, ks,
-                                cyc->segs, cyc->walk, acc, count); break;
+    case 3: hipLaunchKernelGGL((mac_cycle_kernel<R, 3, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
+                               c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+    case 4: hipLaunchKernelGGL((mac_cycle_kernel<R, 4, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
+                               c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+    default: hipLaunchKernelGGL((mac_cycle_kernel<R, 6, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
+                                c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+    }
+}
+
+template <int R, bool FOLD>
+static void launch_mac_cycle_r(int cb, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x,
+                               u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
+                               const CycleTable *cyc, u64 *acc, u64 count)
+{
+    if (cb == 16) launch_mac_cycle_cb<R, 16, FOLD>(dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+    else launch_mac_cycle_cb<R, 8, FOLD>(dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+}
+
+// ciphertexts per cycle-walk workgroup: 8 or 16 (tuning "mac_cycle_cts")
+static void launch_mac_cycle(const Ctx *c, int R, u64 nseg, hipStream_t s, const u64 *x, u64 x_stride,
+                             const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks, const CycleTable *cyc,
+                             u64 *acc, u64 count)
+{
+    const int cb = c->tune.mac_cycle_cts == 16 ? 16 : 8;
+    dim3 grid((u32)nseg, (u32)c->ne, (u32)((count + cb - 1) / cb));
+    if (R == 3) {
+        if (c0) launch_mac_cycle_r<3, true>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        else launch_mac_cycle_r<3, false>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+    } else {
+        if (c0) launch_mac_cycle_r<7, true>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        else launch_mac_cycle_r<7, false>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
     }
 }
 
@@ -420,10 +454,12 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
             // of mac_kernel hit the same few tiles in cache
             const bool cyc = c->tune.mac_cycle && G.cyc && G.cyc->nseg > 0 && (G.n == 3 || G.n == 7) &&
                              (dnum == 3 || dnum == 4 || dnum == 6) && G.cyc->min_len >= c->tune.mac_cycle_min;
+            // the walk folds sum_t phi_t(c0) into the accumulator (then the
+            // combine kernel skips it)
+            const u64 *c0_fold = cyc && c->tune.mac_cycle_c0 && G.c0src ? G.c0src + b0 * G.c0_stride : nullptr;
             if (cyc) {
-                dim3 grid((u32)G.cyc->nseg, (u32)ne, (u32)((B + MAC_CB - 1) / MAC_CB)), block(KS_CYC_TILE, MAC_CB);
-                if (G.n == 3) launch_mac_cycle<3>(dnum, grid, block, s, c->dp, xb, x_stride, raised, ks, G.cyc, acc, B);
-                else launch_mac_cycle<7>(dnum, grid, block, s, c->dp, xb, x_stride, raised, ks, G.cyc, acc, B);
+                launch_mac_cycle(c, G.n, (u64)G.cyc->nseg, s, xb, x_stride, raised, c0_fold, G.c0_stride, ks, G.cyc,
+                                 acc, B);
             } else if (c->tune.mac_cts == 16)
                 hipLaunchKernelGGL((mac_kernel<16>), dim3(blocks_for((u64)ne * N), (u32)((B + 15) / 16)),
                                    dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
@@ -438,7 +474,7 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
             if ((rc = launch_ntt_fwd(c, PolyBatch{v, B * 2, nq, (u64)nq, 0, 0}, s))) return rc;
             hipLaunchKernelGGL(ks_combine_kernel, dim3(blocks_for((u64)nq * N), (u32)B), dim3(KS_THREADS), 0, s,
                                c->dp, acc, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride,
-                               G.c0src ? G.c0src + b0 * G.c0_stride : nullptr, G.c0_stride, ks,
+                               (G.c0src && !c0_fold) ? G.c0src + b0 * G.c0_stride : nullptr, G.c0_stride, ks,
                                G.out + b0 * G.out_stride, G.out_stride, B);
             LC_HIP(c, hipGetLastError());
         }

@@ -321,13 +321,15 @@ def test_rotate_sum_cycle_walk_bitexact(torch, L, oracle_mod, prm, plan):
     cts = ora.encrypt(5, 0, m, keys["pk"])
     want = [ora.rotate_sum(cts[c], plan, [keys["rot"][k] for k in steps]) for c in (0, 7, 10)]
     ctx.set_tuning("mac_cycle_min", 1)  # every block walks, even one-tile cycles
-    for cyc in (1, 0):
+    for cyc, cts_per_wg, fold in ((1, 8, 1), (1, 16, 1), (1, 8, 0), (1, 16, 0), (0, 8, 1)):
         ctx.set_tuning("mac_cycle", cyc)
+        ctx.set_tuning("mac_cycle_cts", cts_per_wg)
+        ctx.set_tuning("mac_cycle_c0", fold)
         g = up(torch, cts)
         ctx.rotate_sum(g, plan)
         got = down(g)
         for w, c in zip(want, (0, 7, 10)):
-            assert np.array_equal(got[c], w), (cyc, c)
+            assert np.array_equal(got[c], w), (cyc, cts_per_wg, fold, c)
 
 
 def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
@@ -342,12 +344,16 @@ def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
     ctx, ora, keys = make_pair(L, O, *prm, seed=23, steps=steps)
     ctx.set_tuning("mac_cycle_min", 1)
     cts = synth.uniform_residues(24, ctx.q, (2, 2, ctx.N))
-    g = up(torch, cts)
-    ctx.rotate_sum(g, plan)
-    got = down(g)
     rks = [keys["rot"][k] for k in steps]
-    for c in range(2):
-        assert np.array_equal(got[c], ora.rotate_sum(cts[c], plan, rks)), c
+    want = [ora.rotate_sum(cts[c], plan, rks) for c in range(2)]
+    for cts_per_wg, fold in ((8, 1), (16, 0)):
+        ctx.set_tuning("mac_cycle_cts", cts_per_wg)
+        ctx.set_tuning("mac_cycle_c0", fold)
+        g = up(torch, cts)
+        ctx.rotate_sum(g, plan)
+        got = down(g)
+        for c in range(2):
+            assert np.array_equal(got[c], want[c]), (cts_per_wg, fold, c)
 
 
 # ---- the pairwise pipeline -----------------------------------------------------------
@@ -483,7 +489,8 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
 def test_set_tuning_rejects_bad_values(L):
     ctx = L.Context(5, (30, 28, 28), (30,), device=0)
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
-                        ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3), ("nope", 1)):
+                        ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
+                        ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
