@@ -454,7 +454,9 @@ def main():
                 bestm = (ms, shp)
         srv.set_tuning("ms_shape", bestm[1])
         tuned["ms_shape"] = bestm[1]
-        for name, values in (("mac_cycle_cts", (8, 16)), ("mac_cycle_c0", (1, 0)), ("mac_cts", (8, 16)),
+        for name, values in (("mac_cycle_short", (1, 0)), ("mac_cycle_cts", (8, 16)), ("mac_short_cts", (16, 8)),
+                             ("mac_cycle_c0", (1, 0)),
+                             ("mac_cts", (8, 16)),
                              ("ks_chunk", (32, 64, 128))):
             bestv = None
             for v in values:

@@ -242,8 +242,12 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * "mac_cycle" (1 = hoisted blocks of 3 or 7 rotations use the cycle-walking
  * inner product that reads each raised digit once; 0 = one gather per key),
  * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used),
- * "mac_cycle_cts" (8/16 ciphertexts per walking workgroup), "mac_cycle_c0"
+ * "mac_cycle_cts" (8/16 ciphertexts per walking workgroup), "mac_short_cts"
+ * (8/16 ciphertexts per short-cycle workgroup), "mac_cycle_c0"
  * (1 = the walk also adds the block's permuted c0 terms; 0 = the combine does),
+ * "mac_cycle_short" (1 = blocks whose tile cycles are at most 2 tiles long,
+ * such as rotations that keep every tile in place, stage each cycle once
+ * instead of walking it),
  * "fuse_modup" (1 = for 2^10 <= N the ModUp base conversion runs inside the
  * first forward-NTT pass of the raised digits; 0 = a kernel of its own),
  * "ms_shape" (masked-sum lanes: 0 = 1 coefficient x 16 rows, 1 = 2 x 8,

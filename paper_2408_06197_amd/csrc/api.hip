@@ -753,9 +753,15 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cycle") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle: 0/1");
         c->tune.mac_cycle = value;
+    } else if (k == "mac_short_cts") {
+        if (value != 8 && value != 16) return fail(c, LC_EINVAL, "mac_short_cts: 8/16");
+        c->tune.mac_short_cts = value;
     } else if (k == "mac_cycle_cts") {
         if (value != 8 && value != 16) return fail(c, LC_EINVAL, "mac_cycle_cts: 8/16");
         c->tune.mac_cycle_cts = value;
+    } else if (k == "mac_cycle_short") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle_short: 0/1");
+        c->tune.mac_cycle_short = value;
     } else if (k == "mac_cycle_c0") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_cycle_c0: 0/1");
         c->tune.mac_cycle_c0 = value;

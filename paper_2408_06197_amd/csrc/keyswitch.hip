@@ -69,6 +69,25 @@ struct KeySet {
     int n;
 };
 
+// ks.key[r] / ks.perm[r] for a per-lane r < R go through LDS: indexing the
+// argument struct with a lane value would load the pointer from memory and
+// stall the wave on every load in flight.  One lane copies them (scalar
+// reads of the arguments); a barrier must follow before they are read.
+typedef const u64 __attribute__((address_space(1))) gu64;  // global memory: loads are not flat
+typedef const u32 __attribute__((address_space(1))) gu32;
+
+template <int R>
+__device__ __forceinline__ void stage_key_ptrs(const KeySet &ks, const u64 **kp, const u32 **pp)
+{
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            kp[k] = ks.key[k];
+            pp[k] = ks.perm[k];
+        }
+    }
+}
+
 // acc[b][k][l][j] = sum_t sum_d X_d[l][perm_t(j)] key_t[d][k][l][j]
 //
 // A lane owns one coefficient (l, j) of MAC_B ciphertexts: each key value is
@@ -99,16 +118,20 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
         u64 src = ks.perm[t] ? ks.perm[t][j] : j;
         const u64 *key = ks.key[t];
         for (int d = 0; d < dp.dnum; d++) {
-            double k0 = u64_to_d(key[((u64)d * 2) * NE + e]);
-            double k1 = u64_to_d(key[((u64)d * 2 + 1) * NE + e]);
+            // all MAC_B loads issued before any is used (a ragged group
+            // re-reads its last ciphertext; those sums are not stored)
             const bool own = d == own_digit;
+            const u64 *xb = own ? x + b0 * x_stride + (u64)l * dp.N + src
+                                : raised + ((b0 * dp.dnum + d) * dp.ne + l) * (u64)dp.N + src;
+            const u64 bstride = own ? x_stride : (u64)dp.dnum * dp.ne * dp.N;
+            const u64 kv0 = key[((u64)d * 2) * NE + e], kv1 = key[((u64)d * 2 + 1) * NE + e];
+            u64 v[MAC_B];
+#pragma unroll
+            for (int b = 0; b < MAC_B; b++) v[b] = xb[(u64)min(b, nb - 1) * bstride];
+            const double k0 = u64_to_d(kv0), k1 = u64_to_d(kv1);
 #pragma unroll
             for (int b = 0; b < MAC_B; b++) {
-                if (b >= nb) break;
-                u64 bb = b0 + b;
-                u64 v = own ? x[bb * x_stride + (u64)l * dp.N + src]
-                            : raised[((bb * dp.dnum + d) * dp.ne + l) * (u64)dp.N + src];
-                double xv = u64_to_d(v);
+                const double xv = u64_to_d(v[b]);
                 a0[b] += mulmod_d(xv, k0, q, qinv);
                 a1[b] += mulmod_d(xv, k1, q, qinv);
             }
@@ -153,7 +176,7 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
 // limbs of accumulator 0 times P mod q (exact after ModDown, which divides
 // by P), and the combine kernel skips its per-key gathers of c0.
 template <int R, int D, int CB, bool FOLD>
-__global__ void __launch_bounds__(KS_CYC_TILE * CB, CB == 8 ? (FOLD ? 2 : 3) : 1)
+__global__ void __launch_bounds__(KS_CYC_TILE * CB, CB == 8 ? 3 : 1)
 mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
                  KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count)
 {
@@ -172,26 +195,41 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     const bool fold = FOLD && l < dp.nq;
     const double pq = fold ? u64_to_d(dp.pmod[l]) : 0.0;
 
+    // The segment's tiles, positions m0 .. m0 + cnt + R - 1, in LDS: the
+    // addresses of every step are then known without a dependent global load.
+    __shared__ u32 tl[KS_CYC_SEG + 8];
+    __shared__ const u64 *kp[R];
+    __shared__ const u32 *pp[R];
+    const int tid = bl * TT + u;
+    for (int k = tid; k < sg.cnt + R; k += TT * CB) tl[k] = walk[sg.base + (sg.m0 + k) % sg.len];
+    stage_key_ptrs<R>(ks, kp, pp);
+    __syncthreads();
+
     // Staging roles: thread row bl stages its ciphertext's D digit values
     // (and c0) at lane u, and (for bl < R) the 2 D key values of key bl + 1
-    // for the output that key serves at this step.  The loads of step p + 1
-    // are in flight while step p computes.
+    // for the output that key serves at this step, with that output's
+    // in-tile source index.  The loads of step p + 1 are in flight while
+    // step p computes: nothing waits on them before the next step's staging.
     const u64 *xraised = raised + (b * D * dp.ne + l) * N + u;
     const u64 *xown = x + b * x_stride + lN + u;
     const u64 *xc0 = fold ? c0 + b * c0_stride + lN + u : nullptr;
-    const u64 *ksrc = bl < R ? ks.key[bl] + lN + u : nullptr;
+    gu64 *ksrc = bl < R ? (gu64 *)kp[bl] + lN + u : nullptr;
+    gu32 *psrc = bl < R ? (gu32 *)pp[bl] + u : nullptr;
+    __shared__ u32 pt[R * TT];  // [R][TT]: in-tile source index of the output key t serves
     u64 xv[XD], kv[2 * D];
+    u32 pk = 0;
     auto fetch = [&](int p) {
-        const u64 src = (u64)walk[sg.base + p % sg.len] * TT;
+        const u64 src = (u64)tl[p - sg.m0] * TT;
 #pragma unroll
         for (int d = 0; d < D; d++)
             xv[d] = live ? (d == own ? xown[src] : xraised[(u64)d * dp.ne * N + src]) : 0;
         if (FOLD) xv[XD - 1] = (live && fold) ? xc0[src] : 0;
         const int m = p - 1 - bl;  // output served by key bl + 1
         const bool kl = bl < R && m >= sg.m0 && m < sg.m0 + sg.cnt;
-        const u64 dst = kl ? (u64)walk[sg.base + m % sg.len] * TT : 0;
+        const u64 dst = kl ? (u64)tl[m - sg.m0] * TT : 0;
 #pragma unroll
         for (int dk = 0; dk < 2 * D; dk++) kv[dk] = kl ? ksrc[(u64)dk * NE + dst] : 0;
+        if (bl < R) pk = psrc[dst];  // in bounds also when !kl (dst = 0); unused then
     };
     auto store = [&]() {
 #pragma unroll
@@ -199,6 +237,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
         if (bl < R) {
 #pragma unroll
             for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
+            pt[bl * TT + u] = pk & (TT - 1);
         }
     };
 
@@ -215,8 +254,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
         for (int t = 1; t <= R; t++) {
             const int m = p - t;
             if (m >= sg.m0 && m < sg.m0 + sg.cnt) {
-                const u64 j = (u64)walk[sg.base + m % sg.len] * TT + u;
-                const double *xs = xt + bl * XD * TT + (ks.perm[t - 1][j] & (TT - 1));
+                const double *xs = xt + bl * XD * TT + pt[(t - 1) * TT + u];
                 const double *kk = kt + (t - 1) * 2 * D * TT + u;
                 double a0 = A[t - 1][0], a1 = A[t - 1][1];
 #pragma unroll
@@ -236,7 +274,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
         }
         const int mo = p - R;  // complete: its key-R contribution was just added
         if (mo >= sg.m0 && live) {
-            const u64 j = (u64)walk[sg.base + mo % sg.len] * TT + u;
+            const u64 j = (u64)tl[mo - sg.m0] * TT + u;
             acc[(b * 2) * NE + lN + j] = d_to_canonical(A[R - 1][0], q, qinv);
             acc[(b * 2 + 1) * NE + lN + j] = d_to_canonical(A[R - 1][1], q, qinv);
         }
@@ -250,12 +288,143 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     }
 }
 
+// Blocks whose tile map has only short cycles (at most LM tiles; one tile:
+// the automorphisms keep every tile in place) need no walk: a workgroup
+// stages all source tiles of its cycle (digits, and c0 when folded) once,
+// then for each output tile of the cycle stages that tile's R keys and adds
+// all R contributions.  Same products and reductions as the walk.
+template <int R, int D, int CB, bool FOLD, int LM>
+__global__ void __launch_bounds__(KS_CYC_TILE * CB)
+mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
+                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count)
+{
+    constexpr int TT = KS_CYC_TILE;
+    constexpr int XD = FOLD ? D + 1 : D;
+    __shared__ double xt[LM * CB * XD * TT];  // [LM][CB][XD][TT]: the cycle's source tiles
+    __shared__ double kt[R * 2 * D * TT];     // [R][2 D][TT]: keys of one output tile
+    const int u = threadIdx.x, bl = threadIdx.y;
+    // With one-tile cycles the walk is the identity (tile i is segment i), so
+    // the tables are not read.
+    int L = 1, base = (int)blockIdx.x;
+    if (LM > 1) {
+        const CycleSeg sg = segs[blockIdx.x];
+        L = sg.len;  // <= LM (checked when the kernel is chosen)
+        base = sg.base;
+    }
+    auto tile = [&](int i) -> u64 { return LM == 1 ? (u64)blockIdx.x : (u64)walk[base + i]; };
+    const int l = blockIdx.y;
+    const u64 b = (u64)blockIdx.z * CB + bl;
+    const bool live = b < count;
+    const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+    const int own = l < dp.nq ? l / dp.alpha : -1;
+    const bool fold = FOLD && l < dp.nq;
+    const double pq = fold ? u64_to_d(dp.pmod[l]) : 0.0;
+
+    // Rows bl < R stage key bl + 1 (2 D values) and its in-tile source
+    // indices for one output tile; the next output's are loaded while this
+    // one computes.
+    static_assert(R < CB, "one key per staging row");
+    __shared__ const u64 *kp[R];
+    __shared__ const u32 *pp[R];
+    stage_key_ptrs<R>(ks, kp, pp);
+    __syncthreads();
+    gu64 *ksrc = bl < R ? (gu64 *)kp[bl] + lN + u : nullptr;
+    gu32 *psrc = bl < R ? (gu32 *)pp[bl] + u : nullptr;
+    __shared__ u32 pt[R * TT];
+    u64 kv[2 * D];
+    u32 pk = 0;
+    auto fetch_keys = [&](int m) {
+        if (bl < R) {
+            const u64 dst = tile(m) * TT;
+#pragma unroll
+            for (int dk = 0; dk < 2 * D; dk++) kv[dk] = ksrc[(u64)dk * NE + dst];
+            pk = psrc[dst];
+        }
+    };
+    auto store_keys = [&]() {
+        if (bl < R) {
+#pragma unroll
+            for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
+            pt[bl * TT + u] = pk & (TT - 1);
+        }
+    };
+    // all loads of the cycle's source tiles in flight before any is used
+    const u64 *xraised = raised + (b * D * dp.ne + l) * N + u;
+    const u64 *xown = x + b * x_stride + lN + u;
+    const u64 *xc0 = fold ? c0 + b * c0_stride + lN + u : nullptr;
+    u64 xv[LM][XD];
+    fetch_keys(0);
+#pragma unroll
+    for (int i = 0; i < LM; i++) {
+        const u64 src = tile(i < L ? i : 0) * TT;
+#pragma unroll
+        for (int d = 0; d < D; d++) xv[i][d] = live ? (d == own ? xown[src] : xraised[(u64)d * dp.ne * N + src]) : 0;
+        if (FOLD) xv[i][XD - 1] = (live && fold) ? xc0[src] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < LM; i++) {  // (slots past the cycle's length are written, never read)
+        double *xs = xt + (i * CB + bl) * XD * TT + u;
+#pragma unroll
+        for (int d = 0; d < XD; d++) xs[d * TT] = u64_to_d(xv[i][d]);
+    }
+    store_keys();
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < LM; m++) {
+        if (m >= L) break;
+        if (m > 0) {
+            __syncthreads();  // the previous output's keys are consumed
+            store_keys();
+            __syncthreads();
+        }
+        if (m + 1 < L) fetch_keys(m + 1);
+        const u64 j = tile(m) * TT + u;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 1
+        for (int t = 1; t <= R; t++) {
+            const int i = LM == 1 ? 0 : (m + t) % L;  // output c_m reads source tile c_{m+t}
+            const double *xs = xt + (i * CB + bl) * XD * TT + pt[(t - 1) * TT + u];
+            const double *kk = kt + (t - 1) * 2 * D * TT + u;
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                const double xd = xs[d * TT];
+                a0 += mulmod_d(xd, kk[(2 * d) * TT], q, qinv);
+                a1 += mulmod_d(xd, kk[(2 * d + 1) * TT], q, qinv);
+                if ((d & 3) == 3) {
+                    a0 = reduce_d(a0, q, qinv);
+                    a1 = reduce_d(a1, q, qinv);
+                }
+            }
+            if (FOLD && fold) a0 += mulmod_d(xs[(XD - 1) * TT], pq, q, qinv);
+            a0 = reduce_d(a0, q, qinv);
+            a1 = reduce_d(a1, q, qinv);
+        }
+        if (live) {
+            acc[(b * 2) * NE + lN + j] = d_to_canonical(a0, q, qinv);
+            acc[(b * 2 + 1) * NE + lN + j] = d_to_canonical(a1, q, qinv);
+        }
+    }
+}
+
 template <int R, int CB, bool FOLD>
-static void launch_mac_cycle_cb(int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x, u64 x_stride,
+static void launch_mac_cycle_cb(int short_lm, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x, u64 x_stride,
                                 const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
                                 const CycleTable *cyc, u64 *acc, u64 count)
 {
     dim3 block(KS_CYC_TILE, CB);
+    if (short_lm == 1 || short_lm == 2) {
+#define LC_SHORT(DD, LMV)                                                                                        \
+    hipLaunchKernelGGL((mac_short_kernel<R, DD, CB, FOLD, LMV>), grid, block, 0, s, dp, x, x_stride, raised, c0, \
+                       c0_stride, ks, cyc->segs, cyc->walk, acc, count)
+        if (short_lm == 1) {
+            if (dnum == 3) LC_SHORT(3, 1); else if (dnum == 4) LC_SHORT(4, 1); else LC_SHORT(6, 1);
+        } else {
+            if (dnum == 3) LC_SHORT(3, 2); else if (dnum == 4) LC_SHORT(4, 2); else LC_SHORT(6, 2);
+        }
+#undef LC_SHORT
+        return;
+    }
     switch (dnum) {
     case 3: hipLaunchKernelGGL((mac_cycle_kernel<R, 3, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
                                c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
@@ -267,27 +436,30 @@ static void launch_mac_cycle_cb(int dnum, dim3 grid, hipStream_t s, const DevPar
 }
 
 template <int R, bool FOLD>
-static void launch_mac_cycle_r(int cb, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x,
+static void launch_mac_cycle_r(int short_lm, int cb, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x,
                                u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
                                const CycleTable *cyc, u64 *acc, u64 count)
 {
-    if (cb == 16) launch_mac_cycle_cb<R, 16, FOLD>(dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-    else launch_mac_cycle_cb<R, 8, FOLD>(dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+    if (cb == 16) launch_mac_cycle_cb<R, 16, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+    else launch_mac_cycle_cb<R, 8, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
 }
 
-// ciphertexts per cycle-walk workgroup: 8 or 16 (tuning "mac_cycle_cts")
+// ciphertexts per workgroup: 8 or 16 (tuning "mac_cycle_cts" for walks,
+// "mac_short_cts" for short cycles)
 static void launch_mac_cycle(const Ctx *c, int R, u64 nseg, hipStream_t s, const u64 *x, u64 x_stride,
                              const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks, const CycleTable *cyc,
                              u64 *acc, u64 count)
 {
-    const int cb = c->tune.mac_cycle_cts == 16 ? 16 : 8;
+    // cycles of at most 2 tiles: no walk (0 = walk)
+    const int short_lm = c->tune.mac_cycle_short && cyc->max_len <= 2 ? cyc->max_len : 0;
+    const int cb = (short_lm ? c->tune.mac_short_cts : c->tune.mac_cycle_cts) == 16 ? 16 : 8;
     dim3 grid((u32)nseg, (u32)c->ne, (u32)((count + cb - 1) / cb));
     if (R == 3) {
-        if (c0) launch_mac_cycle_r<3, true>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-        else launch_mac_cycle_r<3, false>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        if (c0) launch_mac_cycle_r<3, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        else launch_mac_cycle_r<3, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
     } else {
-        if (c0) launch_mac_cycle_r<7, true>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-        else launch_mac_cycle_r<7, false>(cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        if (c0) launch_mac_cycle_r<7, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        else launch_mac_cycle_r<7, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
     }
 }
 
@@ -310,7 +482,7 @@ int build_cycle_table(Ctx *c, u64 g)
             std::vector<u32> walk;
             std::vector<CycleSeg> segs;
             std::vector<char> seen(nt, 0);
-            int min_len = (int)nt;
+            int min_len = (int)nt, max_len = 0;
             for (u64 o = 0; o < nt; o++) {
                 if (seen[o]) continue;
                 const int base = (int)walk.size();
@@ -320,6 +492,7 @@ int build_cycle_table(Ctx *c, u64 g)
                 }
                 const int len = (int)walk.size() - base;
                 min_len = std::min(min_len, len);
+                max_len = std::max(max_len, len);
                 for (int m0 = 0; m0 < len; m0 += KS_CYC_SEG)
                     segs.push_back(CycleSeg{base, len, m0, std::min(KS_CYC_SEG, len - m0)});
             }
@@ -334,6 +507,7 @@ int build_cycle_table(Ctx *c, u64 g)
                 tab.segs = ds;
                 tab.nseg = (int)segs.size();
                 tab.min_len = min_len;
+                tab.max_len = max_len;  // 1: walk[i] = i, which the short-cycle kernel relies on
             }
         }
     }
@@ -453,7 +627,9 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
             // the walk pays off on long cycles; on short ones the per-key gathers
             // of mac_kernel hit the same few tiles in cache
             const bool cyc = c->tune.mac_cycle && G.cyc && G.cyc->nseg > 0 && (G.n == 3 || G.n == 7) &&
-                             (dnum == 3 || dnum == 4 || dnum == 6) && G.cyc->min_len >= c->tune.mac_cycle_min;
+                             (dnum == 3 || dnum == 4 || dnum == 6) &&
+                             (G.cyc->min_len >= c->tune.mac_cycle_min ||
+                              (G.cyc->max_len <= 2 && c->tune.mac_cycle_short));
             // the walk folds sum_t phi_t(c0) into the accumulator (then the
             // combine kernel skips it)
             const u64 *c0_fold = cyc && c->tune.mac_cycle_c0 && G.c0src ? G.c0src + b0 * G.c0_stride : nullptr;

@@ -321,39 +321,46 @@ def test_rotate_sum_cycle_walk_bitexact(torch, L, oracle_mod, prm, plan):
     cts = ora.encrypt(5, 0, m, keys["pk"])
     want = [ora.rotate_sum(cts[c], plan, [keys["rot"][k] for k in steps]) for c in (0, 7, 10)]
     ctx.set_tuning("mac_cycle_min", 1)  # every block walks, even one-tile cycles
-    for cyc, cts_per_wg, fold in ((1, 8, 1), (1, 16, 1), (1, 8, 0), (1, 16, 0), (0, 8, 1)):
+    for cyc, cts_per_wg, fold, one in ((1, 8, 1, 1), (1, 16, 1, 1), (1, 8, 0, 1), (1, 16, 0, 0), (1, 8, 1, 0),
+                                       (0, 8, 1, 1)):
         ctx.set_tuning("mac_cycle", cyc)
         ctx.set_tuning("mac_cycle_cts", cts_per_wg)
+        ctx.set_tuning("mac_short_cts", cts_per_wg)
         ctx.set_tuning("mac_cycle_c0", fold)
+        ctx.set_tuning("mac_cycle_short", one)  # 1: cycles of <= 2 tiles take the no-walk kernel
         g = up(torch, cts)
         ctx.rotate_sum(g, plan)
         got = down(g)
         for w, c in zip(want, (0, 7, 10)):
-            assert np.array_equal(got[c], w), (cyc, cts_per_wg, fold, c)
+            assert np.array_equal(got[c], w), (cyc, cts_per_wg, fold, one, c)
 
 
 def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
     """N = 2^16, 24 + 4 limbs (dnum 6), the (3,3,3,3,3) plan that the bench
     autotunes to: cycles of the tile map up to 1024 tiles, several segments
-    per cycle; two ciphertexts against the oracle."""
+    per cycle, and a last block (rotations by multiples of 2^12) whose tile
+    map is the identity; two ciphertexts against the oracle."""
     O = oracle_mod
     prm = (16, (50,) * 24, (50,) * 4)
     plan = [3, 3, 3, 3, 3]
     ora0 = O.Oracle(*prm)
     steps = ora0.rotsum_steps(plan)
     ctx, ora, keys = make_pair(L, O, *prm, seed=23, steps=steps)
-    ctx.set_tuning("mac_cycle_min", 1)
     cts = synth.uniform_residues(24, ctx.q, (2, 2, ctx.N))
     rks = [keys["rot"][k] for k in steps]
     want = [ora.rotate_sum(cts[c], plan, rks) for c in range(2)]
-    for cts_per_wg, fold in ((8, 1), (16, 0)):
+    # (shortest walked cycle, ciphertexts per workgroup, c0 folded, short cycles without a walk)
+    for cmin, cts_per_wg, fold, one in ((1, 8, 1, 0), (1, 16, 0, 1), (16, 16, 1, 1), (16, 8, 0, 1)):
+        ctx.set_tuning("mac_cycle_min", cmin)
         ctx.set_tuning("mac_cycle_cts", cts_per_wg)
+        ctx.set_tuning("mac_short_cts", 24 - cts_per_wg)  # the other width
         ctx.set_tuning("mac_cycle_c0", fold)
+        ctx.set_tuning("mac_cycle_short", one)
         g = up(torch, cts)
         ctx.rotate_sum(g, plan)
         got = down(g)
         for c in range(2):
-            assert np.array_equal(got[c], want[c]), (cts_per_wg, fold, c)
+            assert np.array_equal(got[c], want[c]), (cmin, cts_per_wg, fold, one, c)
 
 
 # ---- the pairwise pipeline -----------------------------------------------------------
@@ -490,7 +497,8 @@ def test_set_tuning_rejects_bad_values(L):
     ctx = L.Context(5, (30, 28, 28), (30,), device=0)
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
                         ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
-                        ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("nope", 1)):
+                        ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("mac_cycle_short", 2), ("mac_short_cts", 4),
+                        ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
