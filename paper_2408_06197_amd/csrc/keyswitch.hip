@@ -594,19 +594,27 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
         u64 *v = acc + B * 2 * ne * N;
         const u64 *xb = x + b0 * x_stride;
         u64 words = (u64)nq * N;
-        hipLaunchKernelGGL(strided_copy_kernel, dim3(blocks_for(words * B)), dim3(KS_THREADS), 0, s, xb, x_stride,
-                           xhat, words, words, B);
-        LC_HIP(c, hipGetLastError());
-        if (c->tune.fuse_modup && c->log_n >= 10) {
-            // the inverse transform's last pass scales limb a by N^-1 (Q_d/q_a)^-1,
-            // leaving the ModUp digits y_a; the forward transform of the raised
-            // limbs computes their base conversion in its first pass
+        const bool fused = c->tune.fuse_modup && c->log_n >= 10 && c->log_n <= 16 && x_stride % N == 0;
+        if (!fused) {
+            hipLaunchKernelGGL(strided_copy_kernel, dim3(blocks_for(words * B)), dim3(KS_THREADS), 0, s, xb, x_stride,
+                               xhat, words, words, B);
+            LC_HIP(c, hipGetLastError());
+        }
+        if (fused) {
+            // the inverse transform reads the input limbs in place (out of
+            // place into xhat); its last pass scales limb a by
+            // N^-1 (Q_d/q_a)^-1, leaving the ModUp digits y_a; the forward
+            // transform of the raised limbs computes their base conversion
+            // in its first pass
             PolyBatch ib{xhat, B, nq, (u64)nq, 0, 0};
-            ib.iscale = c->dp.up_scale;
+            ib.iscale = c->dp.ks_scale;
+            ib.in_base = xb;
+            ib.in_gstride = x_stride / N;
             if ((rc = launch_ntt_inv(c, ib, s))) return rc;
             PolyBatch fb{raised, B * dnum, ne, (u64)ne, 0, 1};
-            fb.modup_y = xhat;
-            fb.modup_y_stride = (u64)nq * N;
+            fb.conv = 1;
+            fb.conv_y = xhat;
+            fb.conv_stride = (u64)nq * N;
             if ((rc = launch_ntt_fwd(c, fb, s))) return rc;
         } else {
             if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
@@ -643,15 +651,39 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                 hipLaunchKernelGGL((mac_kernel<8>), dim3(blocks_for((u64)ne * N), (u32)((B + 7) / 8)),
                                    dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
             LC_HIP(c, hipGetLastError());
-            if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
-            hipLaunchKernelGGL(moddown_bconv_kernel, dim3(blocks_for(B * 2 * N)), dim3(KS_THREADS), 0, s, c->dp, acc,
-                               v, B);
-            LC_HIP(c, hipGetLastError());
-            if ((rc = launch_ntt_fwd(c, PolyBatch{v, B * 2, nq, (u64)nq, 0, 0}, s))) return rc;
+            const u64 *c0rest = (G.c0src && !c0_fold) ? G.c0src + b0 * G.c0_stride : nullptr;
+            if (fused && np <= 6) {
+                // ModDown in two transforms: the inverse one scales P limb k by
+                // N^-1 (P / p_k)^-1 (in place in acc); the forward one computes
+                // the conversion to the Q limbs in its first pass and, unless
+                // permuted c0 terms remain, the combine in its last
+                PolyBatch ib{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0};
+                ib.iscale = c->dp.ks_scale;
+                if ((rc = launch_ntt_inv(c, ib, s))) return rc;
+                PolyBatch fb{v, B * 2, nq, (u64)nq, 0, 0};
+                fb.conv = 2;
+                fb.conv_y = acc + (u64)nq * N;
+                fb.conv_stride = (u64)ne * N;
+                if (!c0rest) {
+                    fb.comb_acc = acc;
+                    fb.comb_acc_stride = (u64)ne * N;
+                    fb.comb_add = G.base ? G.base + b0 * G.base_stride : nullptr;
+                    fb.comb_add_stride = G.base_stride;
+                    fb.comb_out = G.out + b0 * G.out_stride;
+                    fb.comb_out_stride = G.out_stride;
+                }
+                if ((rc = launch_ntt_fwd(c, fb, s))) return rc;
+                if (!c0rest) continue;
+            } else {
+                if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
+                hipLaunchKernelGGL(moddown_bconv_kernel, dim3(blocks_for(B * 2 * N)), dim3(KS_THREADS), 0, s, c->dp,
+                                   acc, v, B);
+                LC_HIP(c, hipGetLastError());
+                if ((rc = launch_ntt_fwd(c, PolyBatch{v, B * 2, nq, (u64)nq, 0, 0}, s))) return rc;
+            }
             hipLaunchKernelGGL(ks_combine_kernel, dim3(blocks_for((u64)nq * N), (u32)B), dim3(KS_THREADS), 0, s,
-                               c->dp, acc, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride,
-                               (G.c0src && !c0_fold) ? G.c0src + b0 * G.c0_stride : nullptr, G.c0_stride, ks,
-                               G.out + b0 * G.out_stride, G.out_stride, B);
+                               c->dp, acc, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride, c0rest,
+                               G.c0_stride, ks, G.out + b0 * G.out_stride, G.out_stride, B);
             LC_HIP(c, hipGetLastError());
         }
     }

@@ -31,7 +31,8 @@ struct DevParams {
     const u64 *up_fac;              // [dnum][alpha][ne]: (Q_d / q_a) mod m_l
     const u64 *dn_inv, *dn_inv_sh;  // [np]: (P / p_k)^-1 mod p_k
     const u64 *dn_fac;              // [np][nq]: (P / p_k) mod q_l
-    const u64 *up_scale;            // [nq]: N^-1 (Q_d / q_a)^-1 mod q_a for limb a of digit d
+    const u64 *ks_scale;            // [ne]: scale of a key switch's last inverse pass: N^-1 (Q_d / q_a)^-1
+                                    // mod q_a for limb a of digit d, N^-1 (P / p_k)^-1 mod p_k for P limb k
     const double *up_inv_d, *up_fac_d, *dn_inv_d, *dn_fac_d;  // the four tables above as doubles
     const u64 *pinv, *pinv_sh;      // [nq]: P^-1 mod q_l
     const u64 *pmod;                // [nq]: P mod q_l (gadget)
@@ -162,12 +163,34 @@ struct PolyBatch {
     int skip_own_digit;
     // inverse only: per-limb scale of the last pass (by absolute limb; NULL = N^-1)
     const u64 *iscale = nullptr;
-    // forward only, groups = (ciphertext, digit) of raised limbs: the first
-    // pass computes its input as the ModUp base conversion of the digit's
-    // limbs of modup_y ([count / dnum][nq][N], already scaled by
-    // (Q_d / q_a)^-1, canonical) instead of reading base
-    const u64 *modup_y = nullptr;
-    u64 modup_y_stride = 0;  // words per ciphertext
+    // forward only, two-pass transforms: the first pass computes its input
+    // as a base conversion (conv = 1: ModUp, 2: ModDown) of canonical
+    // residues in conv_y instead of reading base.
+    //   ModUp: groups = (ciphertext, digit) of raised limbs; conv_y is
+    //     [count / dnum][nq][N] (conv_stride words per ciphertext), limb a of
+    //     digit d already scaled by (Q_d / q_a)^-1.
+    //   ModDown: groups = (ciphertext, component) of nq limbs; conv_y holds
+    //     each group's np limbs (conv_stride words per group), limb k
+    //     already scaled by (P / p_k)^-1.
+    int conv = 0;
+    const u64 *conv_y = nullptr;
+    u64 conv_stride = 0;
+    // forward only, two-pass transforms, groups = (ciphertext, component)
+    // of nq limbs: the last pass writes the ModDown result
+    //   comb_out = (comb_acc - this transform) P^-1 (+ comb_add)
+    // instead of base.  comb_acc: comb_acc_stride words per group;
+    // comb_add / comb_out: stride words per ciphertext, component 1 at +nq N.
+    const u64 *comb_acc = nullptr;
+    u64 comb_acc_stride = 0;
+    const u64 *comb_add = nullptr;
+    u64 comb_add_stride = 0;
+    u64 *comb_out = nullptr;
+    u64 comb_out_stride = 0;
+    // two-pass transforms (2^10 <= N <= 2^16) only: the first pass reads
+    // group g, limb l from in_base + (g in_gstride + l) N instead of base
+    // (an out-of-place transform; in_base is not written)
+    const u64 *in_base = nullptr;
+    u64 in_gstride = 0;  // in polynomials
 };
 int launch_ntt_fwd(Ctx *c, const PolyBatch &b, hipStream_t s);
 int launch_ntt_inv(Ctx *c, const PolyBatch &b, hipStream_t s);

@@ -29,13 +29,15 @@ struct PassArgs {
     int final_;  // last pass of the transform: canonicalize (and scale by N^-1 when inverse)
 };
 
-__device__ __forceinline__ bool poly_of_block(const DevParams &dp, const PolyBatch &pb, u64 p, u64 *&ptr, int &mi)
+__device__ __forceinline__ bool poly_of_block(const DevParams &dp, const PolyBatch &pb, u64 p, u64 *&ptr, int &mi,
+                                              const u64 **in = nullptr)
 {
     u64 g = p / (u64)pb.nlimb;
     int l = (int)(p % (u64)pb.nlimb);
     mi = pb.limb0 + l;
     if (pb.skip_own_digit && mi < dp.nq && (int)(g % (u64)dp.dnum) == mi / dp.alpha) return false;
     ptr = pb.base + (g * pb.gstride + (u64)l) * dp.N;
+    if (in) *in = pb.in_base ? pb.in_base + (g * pb.in_gstride + (u64)l) * dp.N : ptr;
     return true;
 }
 
@@ -168,7 +170,10 @@ __device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 
 
 // first_: the pass reads uint64 residues (else doubles left by the other pass);
 // final_: the pass writes canonical uint64 residues (times N^-1 when inverse).
-template <int LOG_S, bool INVERSE, bool BLOCKS, bool FUSED_MODUP = false>
+// MODE (forward only): 1 / 2 = first pass with the ModUp / ModDown base
+// conversion (PolyBatch::conv), 3 = last pass with the ModDown combine
+// (PolyBatch::comb_*).
+template <int LOG_S, bool INVERSE, bool BLOCKS, int MODE = 0>
 __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
 {
     constexpr u32 S = 1u << LOG_S;
@@ -178,22 +183,24 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
     u64 *poly;
     int mi;
     u64 pidx = blockIdx.x;
-    if (FUSED_MODUP && (pb.count & 7) == 0) {
+    if ((MODE == 1 || MODE == 2) && (pb.count & 7) == 0) {
         // workgroups are dealt to the 8 XCDs round-robin: remap so that the
-        // limbs of one (ciphertext, digit) group run on one XCD and share its
-        // L2 copy of the group's ModUp digits
+        // limbs of one group run on one XCD and share its L2 copy of the
+        // group's conversion inputs
         const u64 j = blockIdx.x >> 3, nl = (u64)pb.nlimb;
         pidx = ((j / nl) * 8 + (blockIdx.x & 7)) * nl + j % nl;
     }
-    if (!poly_of_block(dp, pb, pidx, poly, mi)) return;
+    const u64 *src;  // what the first pass reads
+    if (!poly_of_block(dp, pb, pidx, poly, mi, &src)) return;
     const double q = dp.mc[mi].qd, qinv = dp.mc[mi].qinv;
+    const bool first_ = !final_;
+    if (!first_) src = poly;
     const u32 tile = blockIdx.y;
     const u32 stride = dp.N >> (s0 + LOG_S);
     const u32 nthreads = blockDim.x;
     const u32 tid = threadIdx.x;
     const u32 nel = S * (u32)cols;
     const double *tw = (INVERSE ? dp.itwd : dp.twd) + (u64)mi * dp.N;
-    const bool first_ = !final_;
     // tile geometry
     u64 hi_col = 0, lo0 = 0;
     if (!BLOCKS) {
@@ -204,20 +211,34 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
     // coalesced load into LDS: every lane issues its eight 16-byte loads
     // (element pairs e, e+1 with e even) before writing any of them
     double v[16];
-    if (FUSED_MODUP) {  // forward, first pass, raised digits
-        // the raised limb's input is the ModUp base conversion of its digit:
-        // sum_a y_a (Q_d / q_a) mod m over the digit's limbs a of modup_y,
-        // where y_a is already [x^_a (Q_d / q_a)^-1]_{q_a}; the sum (|s| <= 7 m)
-        // is reduced to |s| <= m / 2 + 1, a valid input of the transform
+    if (MODE == 1 || MODE == 2) {  // forward, first pass, base conversion
+        // the limb's input is the base conversion sum_a y_a F_a mod m over
+        // the source limbs a of conv_y, each y_a already scaled by its
+        // inverse factor (ModUp: the digit's limbs, F_a = Q_d / q_a; ModDown:
+        // the P limbs, F_k = P / p_k); the sum (|s| <= 7 m) is reduced to
+        // |s| <= m / 2 + 1, a valid input of the transform
         const u64 grp = pidx / (u64)pb.nlimb;
-        const int d = (int)(grp % (u64)dp.dnum);
-        const int a0 = d * dp.alpha, na = min(dp.alpha, dp.nq - a0);
-        const u64 *yb = pb.modup_y + (grp / (u64)dp.dnum) * pb.modup_y_stride + (u64)a0 * dp.N;
-        const double *fac = dp.up_fac_d + (u64)d * dp.alpha * dp.ne + mi;
+        const u64 *yb;
+        const double *fac;
+        u64 fstride;
+        int na;
+        if (MODE == 1) {
+            const int d = (int)(grp % (u64)dp.dnum);
+            const int a0 = d * dp.alpha;
+            na = min(dp.alpha, dp.nq - a0);
+            yb = pb.conv_y + (grp / (u64)dp.dnum) * pb.conv_stride + (u64)a0 * dp.N;
+            fac = dp.up_fac_d + (u64)d * dp.alpha * dp.ne + mi;
+            fstride = (u64)dp.ne;
+        } else {
+            na = dp.np;
+            yb = pb.conv_y + grp * pb.conv_stride;
+            fac = dp.dn_fac_d + mi;
+            fstride = (u64)dp.nq;
+        }
 #pragma unroll
         for (int i = 0; i < 16; i++) v[i] = 0.0;
         for (int a = 0; a < na; a++) {
-            const double f = fac[(u64)a * dp.ne];
+            const double f = fac[(u64)a * fstride];
             ulonglong2 y2[8];
 #pragma unroll
             for (int i = 0; i < 8; i++) {
@@ -242,7 +263,7 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
             u64 g;
             if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
             else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
-            ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(poly + g);
+            ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(src + g);
             v[2 * i] = first_ ? u64_to_d(p2.x) : __longlong_as_double((long long)p2.x);
             v[2 * i + 1] = first_ ? u64_to_d(p2.y) : __longlong_as_double((long long)p2.y);
         }
@@ -279,6 +300,41 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         __syncthreads();
     }
     const double ni = (double)(pb.iscale ? pb.iscale[mi] : dp.ninv[mi]);
+    if (MODE == 3) {  // forward, last pass: the ModDown combine
+        // out = (acc - v) P^-1 (+ add) with v this transform's output:
+        // |acc - v| < 4 q, so the product and the sum stay exact
+        const u64 grp = pidx / (u64)pb.nlimb, lN = (u64)mi * dp.N, half = (u64)dp.nq * dp.N;
+        const u64 *accp = pb.comb_acc + grp * pb.comb_acc_stride + lN;
+        const u64 *addp = pb.comb_add ? pb.comb_add + (grp >> 1) * pb.comb_add_stride + (grp & 1) * half + lN
+                                      : nullptr;
+        u64 *outp = pb.comb_out + (grp >> 1) * pb.comb_out_stride + (grp & 1) * half + lN;
+        const double pinv = u64_to_d(dp.pinv[mi]);
+        ulonglong2 a2[8], b2[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const u32 e = 2 * (tid + (u32)i * nthreads);
+            const u64 g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
+            a2[i] = *reinterpret_cast<const ulonglong2 *>(accp + g);
+            if (addp) b2[i] = *reinterpret_cast<const ulonglong2 *>(addp + g);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const u32 e = 2 * (tid + (u32)i * nthreads);
+            const u32 cc = e >> LOG_S, a = e & (S - 1);
+            const u64 g = ((u64)tile * cols + cc) * S + a;
+            double r0 = mulmod_d(u64_to_d(a2[i].x) - lds[lds_idx<LOG_S>(cc, a)], pinv, q, qinv);
+            double r1 = mulmod_d(u64_to_d(a2[i].y) - lds[lds_idx<LOG_S>(cc, a + 1)], pinv, q, qinv);
+            if (addp) {
+                r0 += u64_to_d(b2[i].x);
+                r1 += u64_to_d(b2[i].y);
+            }
+            ulonglong2 o;
+            o.x = d_to_canonical(r0, q, qinv);
+            o.y = d_to_canonical(r1, q, qinv);
+            *reinterpret_cast<ulonglong2 *>(outp + g) = o;
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         u32 e = 2 * (tid + (u32)i * nthreads);
@@ -320,15 +376,15 @@ static int plan_fast(int log_n, FastPass *p)
     return 2;
 }
 
-template <bool INV, bool BLOCKS, bool FUSED = false>
+template <bool INV, bool BLOCKS, int MODE = 0>
 static void launch_fast_one(int log_s, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &dp,
                             const PolyBatch &b, int s0, int cols, int final_)
 {
     switch (log_s) {
-    case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, FUSED>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     }
 }
 
@@ -359,8 +415,12 @@ static int launch_fast(Ctx *c, const PolyBatch &b, const FastPass *fp, hipStream
         if (inverse) {
             if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
             else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
-        } else if (k == 0 && b.modup_y) {  // first forward pass (columns) with the ModUp conversion
-            launch_fast_one<false, false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        } else if (k == 0 && b.conv == 1) {  // first forward pass (columns) with the ModUp conversion
+            launch_fast_one<false, false, 1>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        } else if (k == 0 && b.conv == 2) {  // ... with the ModDown conversion
+            launch_fast_one<false, false, 2>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
+        } else if (k == 1 && b.comb_out) {  // last forward pass (blocks) with the ModDown combine
+            launch_fast_one<false, true, 3>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
         } else {
             if (P.blocks) launch_fast_one<false, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
             else launch_fast_one<false, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
@@ -386,18 +446,27 @@ static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
             const u64 group_bytes = (u64)b.nlimb * c->N * sizeof(u64);
             gsub = std::max<u64>(1, ((u64)c->tune.ntt_sub_kb << 10) / group_bytes);
             if (b.skip_own_digit) gsub = std::max<u64>((u64)c->dnum, gsub / c->dnum * c->dnum);
+            if (b.comb_out) gsub = std::max<u64>(2, gsub / 2 * 2);  // whole ciphertexts
         }
         for (u64 g0 = 0; g0 < b.count; g0 += gsub) {
             PolyBatch sb = b;
             sb.base = b.base + g0 * b.gstride * c->N;
+            if (b.in_base) sb.in_base = b.in_base + g0 * b.in_gstride * c->N;
             sb.count = std::min(gsub, b.count - g0);
-            if (b.modup_y) sb.modup_y = b.modup_y + (g0 / (u64)c->dnum) * b.modup_y_stride;  // g0 % dnum == 0
+            if (b.conv == 1) sb.conv_y = b.conv_y + (g0 / (u64)c->dnum) * b.conv_stride;  // g0 % dnum == 0
+            if (b.conv == 2) sb.conv_y = b.conv_y + g0 * b.conv_stride;
+            if (b.comb_out) {  // groups are (ciphertext, component): g0 is even
+                sb.comb_acc = b.comb_acc + g0 * b.comb_acc_stride;
+                if (b.comb_add) sb.comb_add = b.comb_add + g0 / 2 * b.comb_add_stride;
+                sb.comb_out = b.comb_out + g0 / 2 * b.comb_out_stride;
+            }
             int rc = launch_fast(c, sb, fp, s, inverse);
             if (rc) return rc;
         }
         return LC_OK;
     }
-    if (b.modup_y) return fail(c, LC_EINVAL, "the fused ModUp transform needs 2^10 <= N <= 2^16");
+    if (b.conv || b.comb_out) return fail(c, LC_EINVAL, "fused key-switch transforms need 2^10 <= N <= 2^16");
+    if (b.in_base) return fail(c, LC_EINVAL, "an out-of-place transform needs 2^10 <= N <= 2^16");
     PassArgs pass[2];
     int np = plan_passes(c->log_n, pass);
     for (int k = 0; k < np; k++) {

@@ -244,32 +244,41 @@ mask_mul_acc_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
 #pragma unroll
     for (int t = 0; t < MA_ROWS; t++) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
     for (int i0 = 0; i0 < n; i0 += 2) {
+        // every load of the round is issued before any is used: rows past len
+        // re-read row len - 1 (their sums are not stored), a missing second
+        // client re-reads the first with a zero mask
+        u64 mv[2][2], cv[2][MA_ROWS][2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const u64 i = (u64)min(i0 + u, n - 1);
+            mv[u][0] = masks[i * 2 * S + r];
+            mv[u][1] = masks[i * 2 * S + S + r];
+#pragma unroll
+            for (int t = 0; t < MA_ROWS; t++) {
+                const u64 *c = cts + i * client_stride + (u64)min(k0 + t, len - 1) * 2 * S + r;
+                cv[u][t][0] = c[0];
+                cv[u][t][1] = c[S];
+            }
+        }
         double m[2][2];
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             const bool live = i0 + u < n;
-            m[u][0] = live ? u64_to_d(masks[(u64)(i0 + u) * 2 * S + r]) : 0.0;
-            m[u][1] = live ? u64_to_d(masks[(u64)(i0 + u) * 2 * S + S + r]) : 0.0;
+            m[u][0] = live ? u64_to_d(mv[u][0]) : 0.0;
+            m[u][1] = live ? u64_to_d(mv[u][1]) : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < MA_ROWS; t++) {
-            if (k0 + t < len) {
 #pragma unroll
-                for (int u = 0; u < 2; u++) {
-                    double a0 = 0.0, a1 = 0.0;
-                    if (i0 + u < n) {
-                        const u64 *c = cts + (u64)(i0 + u) * client_stride + (u64)(k0 + t) * 2 * S + r;
-                        a0 = u64_to_d(c[0]);
-                        a1 = u64_to_d(c[S]);
-                    }
-                    acc[t][0] += mulmod_d(a0, m[u][0], q, qinv);
-                    acc[t][1] += mulmod_d(a0, m[u][1], q, qinv) + mulmod_d(a1, m[u][0], q, qinv);
-                    acc[t][2] += mulmod_d(a1, m[u][1], q, qinv);
-                }
-                acc[t][0] = reduce_d(acc[t][0], q, qinv);
-                acc[t][1] = reduce_d(acc[t][1], q, qinv);
-                acc[t][2] = reduce_d(acc[t][2], q, qinv);
+            for (int u = 0; u < 2; u++) {
+                const double a0 = u64_to_d(cv[u][t][0]), a1 = u64_to_d(cv[u][t][1]);
+                acc[t][0] += mulmod_d(a0, m[u][0], q, qinv);
+                acc[t][1] += mulmod_d(a0, m[u][1], q, qinv) + mulmod_d(a1, m[u][0], q, qinv);
+                acc[t][2] += mulmod_d(a1, m[u][1], q, qinv);
             }
+            acc[t][0] = reduce_d(acc[t][0], q, qinv);
+            acc[t][1] = reduce_d(acc[t][1], q, qinv);
+            acc[t][2] = reduce_d(acc[t][2], q, qinv);
         }
     }
 #pragma unroll

@@ -248,9 +248,8 @@ int build_params(Ctx *c, const lc_params *prm)
             }
         }
     }
-    std::vector<u64> ups(nq);
+    std::vector<u64> ups(ne);
     for (int l = 0; l < nq; l++) ups[l] = mulm(ninv[l], upi[(size_t)(l / alpha) * alpha + l % alpha], c->mod[l]);
-    d.up_scale = upload(c, ups);
     d.up_inv = upload(c, upi);
     d.up_inv_sh = upload(c, upis);
     d.up_fac = upload(c, upf);
@@ -279,6 +278,8 @@ int build_params(Ctx *c, const lc_params *prm)
         pinv[l] = invm(P, m);
         pinvs[l] = shoup_of(pinv[l], m);
     }
+    for (int k = 0; k < np; k++) ups[nq + k] = mulm(ninv[nq + k], dni[k], c->mod[nq + k]);
+    d.ks_scale = upload(c, ups);
     d.dn_inv = upload(c, dni);
     d.dn_inv_sh = upload(c, dnis);
     d.dn_fac = upload(c, dnf);
@@ -294,7 +295,7 @@ int build_params(Ctx *c, const lc_params *prm)
     c->cdt_host = cdt;
 
     if (c->device < 0) return LC_OK;
-    if (!d.twd || !d.itwd || !d.up_inv_d || !d.up_fac_d || !d.dn_inv_d || !d.dn_fac_d || !d.up_scale)
+    if (!d.twd || !d.itwd || !d.up_inv_d || !d.up_fac_d || !d.dn_inv_d || !d.dn_fac_d || !d.ks_scale)
         return fail(c, LC_ENOMEM, "could not upload parameter tables");
     if (!d.mc || !d.tw || !d.tw_sh || !d.itw || !d.itw_sh || !d.ninv || !d.ninv_sh || !d.up_inv || !d.up_inv_sh ||
         !d.up_fac || !d.dn_inv || !d.dn_inv_sh || !d.dn_fac || !d.pinv || !d.pinv_sh || !d.pmod || !d.cdt)
