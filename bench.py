@@ -37,8 +37,8 @@ A2_OPS_PER_UPDATE = 23
 # (FETCH_SIZE 2.0x low, WRITE_SIZE exact); see
 # profiles/pair_triples_n65536_l24_20clients_pmc.txt.  Valid only for the
 # kernel source it was taken on: the section of ops.hip is hashed at run time.
-A2_PMC = {"fetch_bytes": 2.0 * 84060000 * 1024, "write_bytes": 7004000 * 1024,
-          "source_sha256": "892510a8240e414f0fed6e594c22992648c6bbaa9fba5a83b35d078492c1d3e5"}
+A2_PMC = {"fetch_bytes": 2.0 * 84056245 * 1024, "write_bytes": 7004160 * 1024,
+          "source_sha256": "3befd0e066be51d74a8af255a29db9337cd30fbb5a83322a4319a836355a7110"}
 
 
 def _a2_source_sha256():

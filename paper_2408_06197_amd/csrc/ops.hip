@@ -333,6 +333,7 @@ int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, con
 
 constexpr int PT_MAXN = 64;     // clients per call
 constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
+constexpr int PT_PF = 8;        // staged elements per thread whose loads are issued together
 constexpr size_t PT_LDS = 64 * 1024;
 
 __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
@@ -380,16 +381,42 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
     for (int r = 0; r < PPT; r++) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
 
     // Staged element e is (client * 2 + comp, kk, t) = (e / ROW, e / T % PT_KB, e % T).
+    // A thread issues the loads of its first PT_PF staged elements together
+    // (unconditional: ciphertexts past len are clamped to the last one and
+    // zeroed when stored) before storing any, so a batch's staging waits for
+    // one round trip rather than one per element.  This needs the regular
+    // launch below; otherwise (and past PT_PF) elements are staged one by one.
     const u64 client_stride = (u64)len * 2 * S;
     const u64 off = (u64)l * N + (u64)blockIdx.x * T;
+    auto src_of = [&](int e, int k0) -> const u64 * {
+        const int t = e % T, kk = (e / T) % PT_KB, rr = e / ROW;
+        const int k = min(k0 + kk, len - 1);
+        return cts + (u64)(rr >> 1) * client_stride + (u64)k * 2 * S + (u64)(rr & 1) * S + off + t;
+    };
+    // When the thread count is a multiple of 2 ROW (the usual launch), a
+    // thread's staged elements share t, kk and the component and step by a
+    // fixed number of clients, so their addresses are one base plus i times
+    // a stride.
+    const bool regular = nthreads % (2 * ROW) == 0;
+    const int kk_t = (tid / T) % PT_KB, rr_t = tid / ROW;
+    const u64 *base_t = cts + (u64)(rr_t >> 1) * client_stride + (u64)(rr_t & 1) * S + off + tid % T;
+    const u64 step_t = (u64)(nthreads / (2 * ROW)) * client_stride;
+    const int imax = (staged - 1 - tid) / nthreads;  // the thread's last element (staged > tid)
     for (int k0 = 0; k0 < len; k0 += PT_KB) {
-        for (int e = tid; e < staged; e += nthreads) {
-            const int t = e % T, kk = (e / T) % PT_KB, rr = e / ROW;
-            double v = 0.0;
-            if (k0 + kk < len)
-                v = u64_to_d(cts[(u64)(rr >> 1) * client_stride + (u64)(k0 + kk) * 2 * S + (u64)(rr & 1) * S + off + t]);
-            tile[e] = v;
+        int e0 = tid;  // first element left to stage
+        if (regular) {
+            u64 sv[PT_PF];
+            const u64 *b = base_t + (u64)min(k0 + kk_t, len - 1) * 2 * S;
+#pragma unroll
+            for (int i = 0; i < PT_PF; i++) sv[i] = b[(u64)min(i, imax) * step_t];
+            const bool live = k0 + kk_t < len;
+#pragma unroll
+            for (int i = 0; i < PT_PF; i++)
+                if (i <= imax) tile[tid + i * nthreads] = live ? u64_to_d(sv[i]) : 0.0;
+            e0 = tid + PT_PF * nthreads;
         }
+        for (int e = e0; e < staged; e += nthreads)
+            tile[e] = k0 + (e / T) % PT_KB < len ? u64_to_d(*src_of(e, k0)) : 0.0;
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < PT_KB; kk++) {
@@ -401,6 +428,9 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
                 acc[r][1] += mulmod_d(x0, x1, q, qinv);
                 acc[r][2] += mulmod_d(x1, x1, q, qinv);
             }
+            // keep the compiler from hoisting every LDS read of the batch
+            // (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int r = 0; r < PPT; r++) {
