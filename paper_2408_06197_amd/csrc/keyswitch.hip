@@ -608,6 +608,7 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
             // in its first pass
             PolyBatch ib{xhat, B, nq, (u64)nq, 0, 0};
             ib.iscale = c->dp.ks_scale;
+            ib.out_f64 = 1;
             ib.in_base = xb;
             ib.in_gstride = x_stride / N;
             if ((rc = launch_ntt_inv(c, ib, s))) return rc;
@@ -659,6 +660,7 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
                 // permuted c0 terms remain, the combine in its last
                 PolyBatch ib{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0};
                 ib.iscale = c->dp.ks_scale;
+                ib.out_f64 = 1;
                 if ((rc = launch_ntt_inv(c, ib, s))) return rc;
                 PolyBatch fb{v, B * 2, nq, (u64)nq, 0, 0};
                 fb.conv = 2;

@@ -163,9 +163,13 @@ struct PolyBatch {
     int skip_own_digit;
     // inverse only: per-limb scale of the last pass (by absolute limb; NULL = N^-1)
     const u64 *iscale = nullptr;
+    // the last pass writes canonical residues as doubles (bit patterns)
+    // instead of uint64: the form the fused conversions below read
+    int out_f64 = 0;
     // forward only, two-pass transforms: the first pass computes its input
     // as a base conversion (conv = 1: ModUp, 2: ModDown) of canonical
-    // residues in conv_y instead of reading base.
+    // residues in conv_y, stored as doubles (out_f64), instead of reading
+    // base.
     //   ModUp: groups = (ciphertext, digit) of raised limbs; conv_y is
     //     [count / dnum][nq][N] (conv_stride words per ciphertext), limb a of
     //     digit d already scaled by (Q_d / q_a)^-1.

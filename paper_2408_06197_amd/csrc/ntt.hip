@@ -250,8 +250,8 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
             }
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                v[2 * i] += mulmod_d(u64_to_d(y2[i].x), f, q, qinv);
-                v[2 * i + 1] += mulmod_d(u64_to_d(y2[i].y), f, q, qinv);
+                v[2 * i] += mulmod_d(__longlong_as_double((long long)y2[i].x), f, q, qinv);
+                v[2 * i + 1] += mulmod_d(__longlong_as_double((long long)y2[i].y), f, q, qinv);
             }
         }
 #pragma unroll
@@ -350,8 +350,13 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
                 d0 = mulmod_d(d0, ni, q, qinv);
                 d1 = mulmod_d(d1, ni, q, qinv);
             }
-            o.x = d_to_canonical(d0, q, qinv);
-            o.y = d_to_canonical(d1, q, qinv);
+            if (pb.out_f64) {
+                o.x = (u64)__double_as_longlong(canon_d(d0, q, qinv));
+                o.y = (u64)__double_as_longlong(canon_d(d1, q, qinv));
+            } else {
+                o.x = d_to_canonical(d0, q, qinv);
+                o.y = d_to_canonical(d1, q, qinv);
+            }
         } else {
             o.x = (u64)__double_as_longlong(d0);
             o.y = (u64)__double_as_longlong(d1);
@@ -465,7 +470,7 @@ static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
         }
         return LC_OK;
     }
-    if (b.conv || b.comb_out) return fail(c, LC_EINVAL, "fused key-switch transforms need 2^10 <= N <= 2^16");
+    if (b.conv || b.comb_out || b.out_f64) return fail(c, LC_EINVAL, "fused key-switch transforms need 2^10 <= N <= 2^16");
     if (b.in_base) return fail(c, LC_EINVAL, "an out-of-place transform needs 2^10 <= N <= 2^16");
     PassArgs pass[2];
     int np = plan_passes(c->log_n, pass);
