@@ -419,7 +419,7 @@ def main():
         trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
         best = None
         for lanes in (16, 32, 64):
-            for ppt in (3, 6):
+            for ppt in (3, 4, 6):
                 srv.set_tuning("pair_lanes", lanes)
                 srv.set_tuning("pair_ppt", ppt)
                 ms = event_time(torch, lambda: srv.pair_triples(cts, out=trip))

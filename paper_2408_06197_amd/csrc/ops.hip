@@ -333,8 +333,9 @@ int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, con
 
 constexpr int PT_MAXN = 64;     // clients per call
 constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
-constexpr int PT_PF = 8;        // staged elements per thread whose loads are issued together
 constexpr size_t PT_LDS = 64 * 1024;
+constexpr int PT_BUF = (int)(PT_LDS / 2 / sizeof(double));  // most doubles per tile buffer
+constexpr int PT_NC = 4;        // most wave copies per wave and batch
 
 __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
 {
@@ -354,7 +355,9 @@ __global__ void __launch_bounds__(1024)
 pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int P, u64 *d01, u64 d01_stride,
                     u64 *d2, u64 d2_stride, int accumulate)
 {
-    extern __shared__ double tile[];  // [n * 2][PT_KB][T]
+    // two tile buffers, each [n * 2][PT_KB][T] (rows of T coefficients,
+    // rounded up to whole wave copies: bufsz doubles)
+    extern __shared__ __attribute__((aligned(16))) double tile0[];
     constexpr int ROW = PT_KB * T;    // doubles per (client, comp)
     const int G = blockDim.y;         // pair groups
     const int lane = threadIdx.x, g = threadIdx.y;
@@ -380,50 +383,76 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
 #pragma unroll
     for (int r = 0; r < PPT; r++) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
 
-    // Staged element e is (client * 2 + comp, kk, t) = (e / ROW, e / T % PT_KB, e % T).
-    // A thread issues the loads of its first PT_PF staged elements together
-    // (unconditional: ciphertexts past len are clamped to the last one and
-    // zeroed when stored) before storing any, so a batch's staging waits for
-    // one round trip rather than one per element.  This needs the regular
-    // launch below; otherwise (and past PT_PF) elements are staged one by one.
+    // Staging of a batch of PT_KB packed ciphertexts.  Row rw = (client * 2 +
+    // comp) * PT_KB + kk of a buffer holds the T coefficients of the tile.
+    // When the thread count is a whole number of waves, each wave copies
+    // groups of 128 / T rows straight from HBM into LDS (16 bytes per lane,
+    // lane i landing 16 i bytes past the group's start: no registers, and the
+    // copy of the next batch runs while this one computes); each lane then
+    // turns the 16 bytes it copied into doubles in place, zeroing packed
+    // ciphertexts past len.  Otherwise each thread stages elements one by one.
     const u64 client_stride = (u64)len * 2 * S;
     const u64 off = (u64)l * N + (u64)blockIdx.x * T;
-    auto src_of = [&](int e, int k0) -> const u64 * {
-        const int t = e % T, kk = (e / T) % PT_KB, rr = e / ROW;
-        const int k = min(k0 + kk, len - 1);
-        return cts + (u64)(rr >> 1) * client_stride + (u64)k * 2 * S + (u64)(rr & 1) * S + off + t;
+    const int nrows = n * 2 * PT_KB;
+    constexpr int RPI = 128 / T;  // rows per wave copy
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthreads >> 6;
+    const int wl = tid & 63, ncopy = (nrows + RPI - 1) / RPI;
+    const bool dma = nthreads % 64 == 0 && (ncopy + nwaves - 1) / nwaves <= PT_NC;
+    double *const tile1 = tile0 + ncopy * RPI * T;
+    auto row_src = [&](int rw, int k0) -> const u64 * {
+        rw = min(rw, nrows - 1);  // rows past the last of a copy group re-read it
+        const int cc = rw / PT_KB, k = min(k0 + rw % PT_KB, len - 1);
+        return cts + (u64)(cc >> 1) * client_stride + (u64)k * 2 * S + (u64)(cc & 1) * S + off;
     };
-    // When the thread count is a multiple of 2 ROW (the usual launch), a
-    // thread's staged elements share t, kk and the component and step by a
-    // fixed number of clients, so their addresses are one base plus i times
-    // a stride.
-    const bool regular = nthreads % (2 * ROW) == 0;
-    const int kk_t = (tid / T) % PT_KB, rr_t = tid / ROW;
-    const u64 *base_t = cts + (u64)(rr_t >> 1) * client_stride + (u64)(rr_t & 1) * S + off + tid % T;
-    const u64 step_t = (u64)(nthreads / (2 * ROW)) * client_stride;
-    const int imax = (staged - 1 - tid) / nthreads;  // the thread's last element (staged > tid)
-    for (int k0 = 0; k0 < len; k0 += PT_KB) {
-        int e0 = tid;  // first element left to stage
-        if (regular) {
-            u64 sv[PT_PF];
-            const u64 *b = base_t + (u64)min(k0 + kk_t, len - 1) * 2 * S;
+    // a wave's copies (at most PT_NC, else the thread stages one by one):
+    // their source addresses without the ciphertext index, computed once
+    const int nmine = dma ? (ncopy - wave + nwaves - 1) / nwaves : 0;
+    const u64 *cbase[PT_NC];
+    int ckk[PT_NC];
 #pragma unroll
-            for (int i = 0; i < PT_PF; i++) sv[i] = b[(u64)min(i, imax) * step_t];
-            const bool live = k0 + kk_t < len;
+    for (int i = 0; i < PT_NC; i++) {
+        const int rw = min((wave + i * nwaves) * RPI + wl / (T / 2), nrows - 1);
+        const int cc = rw / PT_KB;
+        ckk[i] = rw % PT_KB;
+        cbase[i] = cts + (u64)(cc >> 1) * client_stride + (u64)(cc & 1) * S + off + (wl % (T / 2)) * 2;
+    }
+    auto issue = [&](int k0, double *buf) {
+        if (!dma) return;
 #pragma unroll
-            for (int i = 0; i < PT_PF; i++)
-                if (i <= imax) tile[tid + i * nthreads] = live ? u64_to_d(sv[i]) : 0.0;
-            e0 = tid + PT_PF * nthreads;
+        for (int i = 0; i < PT_NC; i++) {
+            if (i >= nmine) break;
+            const u64 *src = cbase[i] + (u64)min(k0 + ckk[i], len - 1) * 2 * S;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)(buf + (wave + i * nwaves) * RPI * T),
+                                             16, 0, 0);
         }
-        for (int e = e0; e < staged; e += nthreads)
-            tile[e] = k0 + (e / T) % PT_KB < len ? u64_to_d(*src_of(e, k0)) : 0.0;
-        __syncthreads();
+    };
+    auto finish = [&](int k0, double *buf) {
+        if (dma) {
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+#pragma unroll
+            for (int i = 0; i < PT_NC; i++) {
+                if (i >= nmine) break;
+                double *d = buf + (wave + i * nwaves) * RPI * T + wl * 2;
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(d);
+                const bool live = k0 + ckk[i] < len;
+                d[0] = live ? u64_to_d(v.x) : 0.0;
+                d[1] = live ? u64_to_d(v.y) : 0.0;
+            }
+        } else {
+            for (int e = tid; e < staged; e += nthreads) {
+                const int rw = e / T;
+                buf[e] = k0 + rw % PT_KB < len ? u64_to_d(row_src(rw, k0)[e % T]) : 0.0;
+            }
+        }
+    };
+    auto compute = [&](const double *tb) {
 #pragma unroll
         for (int kk = 0; kk < PT_KB; kk++) {
 #pragma unroll
             for (int r = 0; r < PPT; r++) {
-                double x0 = tile[oa[r] + kk * T] - tile[ob[r] + kk * T];
-                double x1 = tile[oa[r] + ROW + kk * T] - tile[ob[r] + ROW + kk * T];
+                double x0 = tb[oa[r] + kk * T] - tb[ob[r] + kk * T];
+                double x1 = tb[oa[r] + ROW + kk * T] - tb[ob[r] + ROW + kk * T];
                 acc[r][0] += mulmod_d(x0, x0, q, qinv);
                 acc[r][1] += mulmod_d(x0, x1, q, qinv);
                 acc[r][2] += mulmod_d(x1, x1, q, qinv);
@@ -438,7 +467,18 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
             acc[r][1] = reduce_d(acc[r][1], q, qinv);
             acc[r][2] = reduce_d(acc[r][2], q, qinv);
         }
+    };
+    // Batch b computes from buffer b % 2 while batch b + 1 is copied into
+    // the other.  One barrier per batch: after it every wave has finished
+    // the conversion of batch b and the compute of batch b - 1, whose buffer
+    // the copies of batch b + 1 then overwrite.
+    issue(0, tile0);
+    for (int k0 = 0, cur = 0; k0 < len; k0 += PT_KB, cur ^= 1) {
+        double *tb = cur ? tile1 : tile0, *nb = cur ? tile0 : tile1;
+        finish(k0, tb);
         __syncthreads();
+        if (k0 + PT_KB < len) issue(k0 + PT_KB, nb);
+        compute(tb);
     }
     const u64 o = (u64)l * N + (u64)blockIdx.x * T + lane;
 #pragma unroll
@@ -486,11 +526,13 @@ int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d0
     // coefficient lanes: the tuned value, at most N, and small enough that the
     // staged tiles of all n clients fit the LDS budget
     int T = c->tune.pair_lanes;
-    while (T > 8 && ((u64)T > c->N || (size_t)n * 2 * PT_KB * T * sizeof(double) > PT_LDS)) T >>= 1;
+    // (wave copies move 128 / T rows: a buffer holds whole copy groups)
+    auto buf_doubles = [&](int t) { return ((size_t)n * 2 * PT_KB * t + 127) / 128 * 128; };
+    while (T > 8 && ((u64)T > c->N || buf_doubles(T) > (size_t)PT_BUF)) T >>= 1;
     int G = std::max(1, std::min((P + ppt - 1) / ppt, 1024 / T));
     int chunks = (P + G * ppt - 1) / (G * ppt);
     dim3 grid((u32)(c->N / T), (u32)c->nq, (u32)chunks), block(T, G);
-    size_t lds = (size_t)n * 2 * PT_KB * T * sizeof(double);
+    size_t lds = 2 * buf_doubles(T) * sizeof(double);  // two tile buffers
     switch (T) {
     case 8: launch_pt<8>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
     case 16: launch_pt<16>(ppt, grid, block, lds, s, c->dp, cts, n, len, P, d01, d01_stride, d2, d2_stride, accumulate); break;
