@@ -37,8 +37,8 @@ A2_OPS_PER_UPDATE = 23
 # (FETCH_SIZE 2.0x low, WRITE_SIZE exact); see
 # profiles/pair_triples_n65536_l24_20clients_pmc.txt.  Valid only for the
 # kernel source it was taken on: the section of ops.hip is hashed at run time.
-A2_PMC = {"fetch_bytes": 2.0 * 84056245 * 1024, "write_bytes": 7004160 * 1024,
-          "source_sha256": "3befd0e066be51d74a8af255a29db9337cd30fbb5a83322a4319a836355a7110"}
+A2_PMC = {"fetch_bytes": 2.0 * 84056231 * 1024, "write_bytes": 7004160 * 1024,
+          "source_sha256": "053a07d31ef910cd5ac1422ddbc85a697023e6b45c1d6a7808d08eaca5695de2"}
 
 
 def _a2_source_sha256():

@@ -103,7 +103,7 @@ struct Ctx {
     // launch-shape tuning (lc_set_tuning)
     struct Tuning {
         int pair_lanes = 16;  // coefficients per workgroup of the pair-triple kernel
-        int pair_ppt = 6;     // pairs per lane (1, 3, 4 or 6)
+        int pair_ppt = 4;     // pairs per lane (1, 3, 4 or 6)
         int ks_chunk = 64;    // ciphertexts per key-switch batch
         int ntt_sub_kb = 0;   // two-pass NTTs run per sub-batch of this many KiB (0: whole batch)
         int mac_cts = 8;      // ciphertexts per lane of the key-switch inner product (8 or 16)

@@ -27,7 +27,7 @@ def _calibration_copy():
     torch.cuda.synchronize()
 
 
-def pair(tune, lanes=16, ppt=6, n=20, ln=342):
+def pair(tune, lanes=16, ppt=4, n=20, ln=342):
     """lc_pair_triples over 20 clients x 342 packed ciphertexts (172 GB)."""
     ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
     for k, v in tune.items():
@@ -38,8 +38,8 @@ def pair(tune, lanes=16, ppt=6, n=20, ln=342):
     for i in range(n):
         cts[i].random_(0, 1 << 49, generator=gen)  # below every 50-bit prime
     trip = torch.empty((n * (n - 1) // 2, 3, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
-    ctx.set_tuning("pair_lanes", lanes)
-    ctx.set_tuning("pair_ppt", ppt)
+    ctx.set_tuning("pair_lanes", tune.get("pair_lanes", lanes))
+    ctx.set_tuning("pair_ppt", tune.get("pair_ppt", ppt))
     ctx.pair_triples(cts, out=trip)
     torch.cuda.synchronize()
     del cts
