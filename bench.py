@@ -5,7 +5,7 @@ client ciphertexts: fused subtract/square/lazy-accumulate over all pairs and
 packed ciphertexts, one relinearization per pair, rotate-and-sum (block plan
 of hoisted rotations), SumDis, the plaintext-mask aggregation of every
 client ciphertext, and the KGC's decryption of the distance ciphertexts.
-Ingest (host FP64 encode + device encryption) happens before the timed
+Ingest (device FP64 encode + device encryption) happens before the timed
 region and is reported separately.
 
 Prints one JSON line (see --help for options).
@@ -380,30 +380,47 @@ def main():
     t_keys = time.perf_counter() - t_setup
     log(f"[bench] {w.name}: keys ready in {t_keys:.1f}s; ingesting {n} clients x {ln} ciphertexts")
 
-    # ---- ingest: host encode (threads), device encryption --------------------
+    # ---- ingest: device encode and encryption (the host encoder is timed on
+    # one client for comparison) ----------------------------------------------
     nq = srv.nq
     cts = torch.empty((n, ln, 2, nq, N), dtype=torch.int64, device="cuda")
     upd_all = np.empty((n, w.dim), dtype=np.float64)
-    pool = cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
-    t_enc_host = t_enc_dev = 0.0
+    t_h2d = t_enc_dev = t_encrypt = 0.0
+    host_cmp = {}
     for i in range(n):
         upd = synth.client_updates(w, clients=[i])[0]
         upd_all[i] = upd
         chunks = synth.pack(upd, w.slots)
         t0 = time.perf_counter()
-        m = np.stack(list(pool.map(lambda c: srv.encode(c, scale), chunks)))
+        z_dev = torch.from_numpy(chunks).cuda()
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        m_dev = torch.from_numpy(m).cuda()
+        m_dev = srv.encode_device(z_dev, scale)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         srv.encrypt(m_dev, seed=w.crypto_seed + 1, first_object=i * ln, out=cts[i])
         torch.cuda.synchronize()
-        t_enc_host += t1 - t0
-        t_enc_dev += time.perf_counter() - t1
-        del m_dev
+        t3 = time.perf_counter()
+        t_h2d += t1 - t0
+        t_enc_dev += t2 - t1
+        t_encrypt += t3 - t2
+        if i == 0:
+            with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+                th = time.perf_counter()
+                m_host = np.stack(list(pool.map(lambda c: srv.encode(c, scale), chunks)))
+                host_cmp["encode_host_s_per_client"] = time.perf_counter() - th
+            d = np.abs(m_dev.cpu().numpy() - m_host)
+            host_cmp["max_coeff_diff"] = int(d.max())
+            host_cmp["coeffs_differing"] = int(np.count_nonzero(d))
+            del m_host, d
+        del z_dev, m_dev
         if (i + 1) % 5 == 0 or i + 1 == n:
             log(f"[bench] ingested {i + 1}/{n} clients")
     ref = fp64_pair_distances(upd_all)
     del upd_all
-    log(f"[bench] ingest: encode {t_enc_host:.1f}s (host), H2D+encrypt {t_enc_dev:.1f}s (device)")
+    log(f"[bench] ingest: H2D {t_h2d:.2f}s, device encode {t_enc_dev:.2f}s, encrypt {t_encrypt:.2f}s; "
+        f"host encode of one client {host_cmp['encode_host_s_per_client']:.2f}s (16 threads), device vs host "
+        f"encode: max diff {host_cmp['max_coeff_diff']}, {host_cmp['coeffs_differing']} coefficients differ")
 
     # ---- buffers -----------------------------------------------------------------
     dist = torch.empty((P, 2, nq, N), dtype=torch.int64, device="cuda")
@@ -753,7 +770,8 @@ def main():
                    "scale_log2": w.scale_log2},
         "check": check,
         "hip_graph": used_graph,
-        "ingest_s": {"encode_host": t_enc_host, "encrypt_device": t_enc_dev, "keygen": t_keys},
+        "ingest_s": {"h2d": t_h2d, "encode_device": t_enc_dev, "encrypt_device": t_encrypt, "keygen": t_keys,
+                     **host_cmp},
         "roofline": roof,
         "cpu_baseline": base,
     }

@@ -123,6 +123,17 @@ int lc_ksk_export(const lc_ctx *ctx, int which, int step, uint64_t *ksk_host);
  * nslots <= N/2 slots (missing slots are zero).  m_host: int64[N]. */
 int lc_encode(const lc_ctx *ctx, const double *z_re, const double *z_im, size_t nslots, double scale,
               int64_t *m_host);
+/* Device encode of `count` real vectors (the f3 ingest path): z_dev is
+ * double[count][z_stride] on the device, of which the first nslots <= N/2
+ * values of each vector are the slots (the rest are zero); m_dev int64[count][N]
+ * receives round(scale * sigma^-1(pi^-1(z))) exactly as lc_encode computes it,
+ * in FP64 on the device (a coefficient within rounding error of a
+ * half-integer may differ by one from lc_encode).  Asynchronous on `stream`.
+ * The first call on a context uploads its transform tables (synchronous).
+ * Scratch: the stream's workspace (up to 256 MiB).  Errors: LC_EINVAL for
+ * nslots > N/2, z_stride < nslots, null buffers or scale <= 0. */
+int lc_encode_device(lc_ctx *ctx, const double *z_dev, size_t count, size_t nslots, size_t z_stride, double scale,
+                     int64_t *m_dev, void *stream);
 /* Decode a coefficient-domain plaintext given as residues [n_q][N] (host):
  * exact CRT to centred integers, then z = pi(sigma(m)) / scale. */
 int lc_decode(const lc_ctx *ctx, const uint64_t *res_host, double scale, double *z_re, double *z_im);

@@ -385,6 +385,16 @@ int lc_encode(const lc_ctx *x, const double *re, const double *im, size_t nslots
     return LC_OK;
 }
 
+int lc_encode_device(lc_ctx *x, const double *z_dev, size_t count, size_t nslots, size_t z_stride, double scale,
+                     int64_t *m_dev, void *stream)
+{
+    CHECK_CTX(x);
+    if (nslots > c->N / 2 || z_stride < nslots) return fail(c, LC_EINVAL, "need nslots <= N/2 and z_stride >= nslots");
+    if (count && ((!z_dev && nslots) || !m_dev)) return fail(c, LC_EINVAL, "null buffer");
+    if (!(scale > 0.0)) return fail(c, LC_EINVAL, "scale must be positive");
+    return launch_encode(c, z_dev, count, nslots, z_stride, scale, m_dev, (hipStream_t)stream);
+}
+
 int lc_decode(const lc_ctx *x, const uint64_t *res, double scale, double *re, double *im)
 {
     if (!x || !res || !re) return LC_EINVAL;

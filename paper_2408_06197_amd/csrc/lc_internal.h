@@ -98,6 +98,10 @@ struct Ctx {
     std::vector<void *> retired;  // outgrown workspace buffers, freed with the context
     size_t retired_bytes = 0;
     std::map<u64, CycleTable> cycles;  // by Galois element
+    // device encode tables (built on first use): exp(-2 pi i j / N),
+    // exp(-i pi k / N) as (re, im) doubles, and the slot of each odd exponent
+    void *enc_w = nullptr, *enc_twist = nullptr;
+    int *enc_slot = nullptr;
     size_t ws_limit = 0;
 
     // launch-shape tuning (lc_set_tuning)
@@ -131,7 +135,7 @@ int hip_fail(Ctx *c, hipError_t e, const char *what);
 
 // device memory owned by the context
 void *dev_alloc(Ctx *c, size_t bytes);
-enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5 };
+enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5, WS_ENCODE = 6 };
 // Pointer to workspace slot `slot` of stream `s` holding at least `bytes`;
 // NULL (with ctx->err set) if it cannot be allocated.  Growing a slot waits
 // for the work already queued on `s`.
@@ -146,6 +150,7 @@ void cdt_thresholds(u64 out[38]);  // cdt.cpp (quad precision)
 
 // host FP64 encode/decode (encode.cpp)
 void encode_host(int log_n, const double *re, const double *im, size_t nslots, double scale, i64 *m);
+int launch_encode(Ctx *c, const double *z, u64 count, u64 nslots, u64 z_stride, double scale, i64 *m, hipStream_t s);
 void decode_host(int log_n, const double *coeff, double scale, double *re, double *im);
 void crt_to_double(const std::vector<u64> &q, const u64 *res, size_t ncoeff, size_t stride, double *out);
 

@@ -51,6 +51,7 @@ _SIGS = {
     "lc_pk_export": [VP, PU64],
     "lc_ksk_export": [VP, INT, INT, PU64],
     "lc_encode": [VP, PD, PD, SZ, _c.c_double, PI64],
+    "lc_encode_device": [VP, VP, SZ, SZ, SZ, _c.c_double, VP, VP],
     "lc_decode": [VP, PU64, _c.c_double, PD, PD],
     "lc_crt_to_double": [VP, PU64, SZ, SZ, PD],
     "lc_gaussian_table": [VP, PU64],
@@ -241,6 +242,20 @@ class Context:
         return out
 
     # ---- device ops ----
+    def encode_device(self, z, scale, out=None, stream=None):
+        """z: float64 device tensor [count, nslots] (real slots, nslots <= N/2,
+        rows contiguous) -> int64 device tensor [count, N] of plaintext
+        coefficients, as `encode` computes them."""
+        import torch
+        if z.dtype != torch.float64 or z.dim() != 2 or z.stride(1) != 1:
+            raise ValueError("z must be a float64 [count, nslots] tensor with contiguous rows")
+        count, nslots = z.shape
+        out = torch.empty((count, self.N), dtype=torch.int64, device=z.device) if out is None else out
+        zp = VP(z.data_ptr()) if z.numel() else None  # rows may be strided (stride(1) == 1 checked above)
+        self._check(lib().lc_encode_device(self._h, zp, count, nslots, z.stride(0) if count > 1 else nslots, scale,
+                                           _ptr(out), _stream(stream)))
+        return out
+
     def encrypt(self, m, seed, first_object=0, out=None, stream=None):
         count = m.shape[0]
         out = self.empty(count, 2, self.nq, self.N) if out is None else out
