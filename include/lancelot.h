@@ -137,6 +137,10 @@ int lc_encode_device(lc_ctx *ctx, const double *z_dev, size_t count, size_t nslo
 /* Decode a coefficient-domain plaintext given as residues [n_q][N] (host):
  * exact CRT to centred integers, then z = pi(sigma(m)) / scale. */
 int lc_decode(const lc_ctx *ctx, const uint64_t *res_host, double scale, double *z_re, double *z_im);
+/* lc_decode for a plaintext at a lower level: residues [nlimb][N] of the
+ * first nlimb Q limbs (1 <= nlimb <= n_q). */
+int lc_decode_level(const lc_ctx *ctx, const uint64_t *res_host, int nlimb, double scale, double *z_re,
+                    double *z_im);
 /* Exact CRT of `ncoeff` coefficients: res_host is [n_q][stride], coefficient
  * t of limb l at res_host[l * stride + t]; out[t] = centred value as double. */
 int lc_crt_to_double(const lc_ctx *ctx, const uint64_t *res_host, size_t ncoeff, size_t stride, double *out);
@@ -156,6 +160,19 @@ int lc_encrypt(lc_ctx *ctx, const int64_t *m_dev, size_t count, uint64_t seed, u
  * Description, decryption; ncomp 3 reads a triple).  in [count][ncomp][n_q][N],
  * out [count][n_q][N].  KGC role. */
 int lc_decrypt(lc_ctx *ctx, const uint64_t *ct_dev, int ncomp, size_t count, uint64_t *pt_dev, void *stream);
+/* lc_decrypt of ciphertexts at a lower level: their first nlimb Q limbs
+ * (1 <= nlimb <= n_q; in [count][ncomp][nlimb][N], out [count][nlimb][N]). */
+int lc_decrypt_level(lc_ctx *ctx, const uint64_t *ct_dev, int ncomp, int nlimb, size_t count, uint64_t *pt_dev,
+                     void *stream);
+/* CKKS rescaling (levels Q_l of the CKKS Scheme Description; the paper uses
+ * the standard operation without spelling it out): for ciphertexts with nlimb
+ * Q limbs q_0 .. q_t (t = nlimb - 1, 2 <= nlimb <= n_q), every coefficient c
+ * of every component becomes the nearest integer to c / q_t modulo
+ * q_0 .. q_{t-1}; the scale drops by the factor q_t.  in [count][ncomp][nlimb][N]
+ * and out [count][ncomp][nlimb - 1][N], NTT domain, ncomp 1..3; out must not
+ * overlap in (LC_EINVAL).  Scratch: the stream's workspace (up to ~1 GiB). */
+int lc_rescale(lc_ctx *ctx, const uint64_t *ct_dev, size_t count, int ncomp, int nlimb, uint64_t *out_dev,
+               void *stream);
 
 /* ---- homomorphic operations (CKKS Scheme Description, evaluation; Methods,
  * Private Distance Evaluation) --------------------------------------------- */

@@ -584,6 +584,36 @@ class Oracle:
         vals = np.array([float(x) for x in self.crt(residues)], dtype=np.float64)
         return decode(vals, self.log_n, scale)
 
+    def rescale(self, ct, nlimb=None):
+        """CKKS rescaling by the last of `nlimb` Q limbs q_t (levels of the
+        CKKS Scheme Description; the operation is the standard one, the paper
+        does not spell it out): every coefficient c of every component, as an
+        integer modulo Q_t = q_0 ... q_t, becomes the nearest integer to
+        c / q_t, reduced modulo q_0 ... q_{t-1}.  ct [ncomp][nlimb][N] in the
+        NTT domain -> [ncomp][nlimb - 1][N] in the NTT domain.  Written from
+        the definition: inverse transform, CRT to Python integers, exact
+        rounded division, reduction, forward transform (q_t is odd, so
+        c / q_t is never a tie)."""
+        ct = _u(ct)
+        nlimb = ct.shape[-2] if nlimb is None else nlimb
+        t = nlimb - 1
+        mods = [int(q) for q in self.q[:nlimb]]
+        qt = mods[t]
+        out = np.zeros(ct.shape[:-2] + (t, self.N), dtype=np.uint64)
+        for comp in range(ct.shape[0]):
+            coef = self.poly_intt(ct[comp, :nlimb])
+            vals = crt_centered(coef, mods)
+            rounded = [(2 * v + qt) // (2 * qt) for v in vals]  # floor(v / qt + 1/2)
+            low = np.array([[r % q for r in rounded] for q in mods[:t]], dtype=np.uint64)
+            out[comp] = self.poly_ntt(low)
+        return out
+
+    def decode_level(self, residues, nlimb, scale):
+        """Decode a coefficient-domain plaintext with residues for the first
+        `nlimb` Q limbs."""
+        vals = np.array([float(x) for x in crt_centered(residues[:nlimb], self.q[:nlimb])], dtype=np.float64)
+        return decode(vals, self.log_n, scale)
+
     def read_distance(self, coeff_residues, scale):
         """Distance from a decrypted rotate-summed ciphertext: after the slot
         sum every slot holds the total, so coefficient 0 equals scale * d."""

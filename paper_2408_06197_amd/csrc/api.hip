@@ -395,6 +395,18 @@ int lc_encode_device(lc_ctx *x, const double *z_dev, size_t count, size_t nslots
     return launch_encode(c, z_dev, count, nslots, z_stride, scale, m_dev, (hipStream_t)stream);
 }
 
+int lc_decode_level(const lc_ctx *x, const uint64_t *res, int nlimb, double scale, double *re, double *im)
+{
+    if (!x || !res || !re) return LC_EINVAL;
+    const Ctx *c = &x->c;
+    if (nlimb < 1 || nlimb > c->nq) return LC_EINVAL;
+    std::vector<u64> q(c->mod.begin(), c->mod.begin() + nlimb);
+    std::vector<double> coeff(c->N);
+    crt_to_double(q, res, c->N, c->N, coeff.data());
+    decode_host(c->log_n, coeff.data(), scale, re, im);
+    return LC_OK;
+}
+
 int lc_decode(const lc_ctx *x, const uint64_t *res, double scale, double *re, double *im)
 {
     if (!x || !res || !re) return LC_EINVAL;
@@ -438,17 +450,35 @@ int lc_encrypt(lc_ctx *x, const int64_t *m, size_t count, uint64_t seed, uint64_
     return LC_OK;
 }
 
-int lc_decrypt(lc_ctx *x, const uint64_t *ct, int ncomp, size_t count, uint64_t *pt, void *stream)
+int lc_decrypt_level(lc_ctx *x, const uint64_t *ct, int ncomp, int nlimb, size_t count, uint64_t *pt, void *stream)
 {
     CHECK_CTX(x);
     if (c->role != LC_ROLE_KGC || !c->sk_ntt) return fail(c, LC_EKEY, "decryption needs the secret key (KGC role)");
     if (ncomp != 2 && ncomp != 3) return fail(c, LC_EINVAL, "ncomp must be 2 or 3");
+    if (nlimb < 1 || nlimb > c->nq) return fail(c, LC_EINVAL, "need 1 <= nlimb <= n_q");
     if (!count) return LC_OK;
     if (!ct || !pt) return fail(c, LC_EINVAL, "null buffer");
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if ((rc = launch_dec_combine(c, ct, ncomp, count, pt, s))) return rc;
-    return launch_ntt_inv(c, PolyBatch{pt, count, c->nq, (u64)c->nq, 0, 0}, s);
+    if ((rc = launch_dec_combine(c, ct, ncomp, nlimb, count, pt, s))) return rc;
+    return launch_ntt_inv(c, PolyBatch{pt, count, nlimb, (u64)nlimb, 0, 0}, s);
+}
+
+int lc_decrypt(lc_ctx *x, const uint64_t *ct, int ncomp, size_t count, uint64_t *pt, void *stream)
+{
+    return lc_decrypt_level(x, ct, ncomp, x ? x->c.nq : 0, count, pt, stream);
+}
+
+int lc_rescale(lc_ctx *x, const uint64_t *ct, size_t count, int ncomp, int nlimb, uint64_t *out, void *stream)
+{
+    CHECK_CTX(x);
+    if (ncomp < 1 || ncomp > 3) return fail(c, LC_EINVAL, "ncomp must be 1..3");
+    if (nlimb < 2 || nlimb > c->nq) return fail(c, LC_EINVAL, "need 2 <= nlimb <= n_q");
+    if (!count) return LC_OK;
+    if (!ct || !out) return fail(c, LC_EINVAL, "null buffer");
+    const u64 in_bytes = (u64)count * ncomp * nlimb * c->N * 8, out_bytes = (u64)count * ncomp * (nlimb - 1) * c->N * 8;
+    if (overlap(ct, in_bytes, out, out_bytes)) return fail(c, LC_EINVAL, "out must not overlap the input");
+    return launch_rescale(c, ct, count, ncomp, nlimb, out, (hipStream_t)stream);
 }
 
 // ---- homomorphic operations -------------------------------------------------------

@@ -36,6 +36,7 @@ struct DevParams {
     const double *up_inv_d, *up_fac_d, *dn_inv_d, *dn_fac_d;  // the four tables above as doubles
     const u64 *pinv, *pinv_sh;      // [nq]: P^-1 mod q_l
     const u64 *pmod;                // [nq]: P mod q_l (gadget)
+    const u64 *rs_inv, *rs_inv_sh;  // [nq][nq]: q_t^-1 mod q_i at [t][i] (i < t), for rescaling by q_t
     const u64 *cdt;                 // [38]: Gaussian thresholds
 };
 
@@ -135,7 +136,7 @@ int hip_fail(Ctx *c, hipError_t e, const char *what);
 
 // device memory owned by the context
 void *dev_alloc(Ctx *c, size_t bytes);
-enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5, WS_ENCODE = 6 };
+enum { WS_KS = 0, WS_PIPE = 1, WS_ROT = 2, WS_ENC = 3, WS_TMP = 4, WS_KEYGEN = 5, WS_ENCODE = 6, WS_RESCALE = 7 };
 // Pointer to workspace slot `slot` of stream `s` holding at least `bytes`;
 // NULL (with ctx->err set) if it cannot be allocated.  Growing a slot waits
 // for the work already queued on `s`.
@@ -151,6 +152,7 @@ void cdt_thresholds(u64 out[38]);  // cdt.cpp (quad precision)
 // host FP64 encode/decode (encode.cpp)
 void encode_host(int log_n, const double *re, const double *im, size_t nslots, double scale, i64 *m);
 int launch_encode(Ctx *c, const double *z, u64 count, u64 nslots, u64 z_stride, double scale, i64 *m, hipStream_t s);
+int launch_rescale(Ctx *c, const u64 *ct, u64 count, int ncomp, int nlimb, u64 *out, hipStream_t s);
 void decode_host(int log_n, const double *coeff, double scale, double *re, double *im);
 void crt_to_double(const std::vector<u64> &q, const u64 *res, size_t ncoeff, size_t stride, double *out);
 
@@ -229,7 +231,7 @@ int launch_pointwise_sq(Ctx *c, const u64 *a, u64 *out, int nlimb, hipStream_t s
 int launch_permute(Ctx *c, const u64 *in, u64 *out, const u32 *perm, u64 npoly, hipStream_t s);
 int launch_enc_sample(Ctx *c, const i64 *m, u64 count, u64 seed, u64 first_object, u64 *tmp, hipStream_t s);
 int launch_enc_combine(Ctx *c, const u64 *tmp, u64 count, u64 *ct, hipStream_t s);
-int launch_dec_combine(Ctx *c, const u64 *ct, int ncomp, u64 count, u64 *out, hipStream_t s);
+int launch_dec_combine(Ctx *c, const u64 *ct, int ncomp, int nlimb, u64 count, u64 *out, hipStream_t s);
 
 // key switching (keyswitch.hip)
 // One output of a hoisted key switch: the key products of all keys in the

@@ -288,6 +288,16 @@ int build_params(Ctx *c, const lc_params *prm)
     d.pinv = upload(c, pinv);
     d.pinv_sh = upload(c, pinvs);
     d.pmod = upload(c, pmod);
+    // rescaling by q_t: q_t^-1 mod q_i for every pair i < t of Q limbs
+    std::vector<u64> rsi((size_t)nq * nq, 0), rsis((size_t)nq * nq, 0);
+    for (int t = 1; t < nq; t++)
+        for (int i = 0; i < t; i++) {
+            const u64 m = c->mod[i];
+            rsi[(size_t)t * nq + i] = invm(c->mod[t] % m, m);
+            rsis[(size_t)t * nq + i] = shoup_of(rsi[(size_t)t * nq + i], m);
+        }
+    d.rs_inv = upload(c, rsi);
+    d.rs_inv_sh = upload(c, rsis);
 
     std::vector<u64> cdt(38);
     cdt_thresholds(cdt.data());
@@ -298,7 +308,8 @@ int build_params(Ctx *c, const lc_params *prm)
     if (!d.twd || !d.itwd || !d.up_inv_d || !d.up_fac_d || !d.dn_inv_d || !d.dn_fac_d || !d.ks_scale)
         return fail(c, LC_ENOMEM, "could not upload parameter tables");
     if (!d.mc || !d.tw || !d.tw_sh || !d.itw || !d.itw_sh || !d.ninv || !d.ninv_sh || !d.up_inv || !d.up_inv_sh ||
-        !d.up_fac || !d.dn_inv || !d.dn_inv_sh || !d.dn_fac || !d.pinv || !d.pinv_sh || !d.pmod || !d.cdt)
+        !d.up_fac || !d.dn_inv || !d.dn_inv_sh || !d.dn_fac || !d.pinv || !d.pinv_sh || !d.pmod || !d.cdt ||
+        !d.rs_inv || !d.rs_inv_sh)
         return fail(c, LC_ENOMEM, "could not upload parameter tables");
     return LC_OK;
 }

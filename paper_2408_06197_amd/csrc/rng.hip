@@ -281,11 +281,11 @@ int launch_enc_combine(Ctx *c, const u64 *tmp, u64 count, u64 *ct, hipStream_t s
 // ---- decryption: c0 + c1 s (+ c2 s^2), NTT domain ---------------------------
 
 __global__ void __launch_bounds__(RNG_THREADS)
-dec_combine_kernel(DevParams dp, const u64 *ct, int ncomp, u64 count, const u64 *s, const u64 *s_sh, const u64 *s2,
-                   const u64 *s2_sh, u64 *out)
+dec_combine_kernel(DevParams dp, const u64 *ct, int ncomp, int nlimb, u64 count, const u64 *s, const u64 *s_sh,
+                   const u64 *s2, const u64 *s2_sh, u64 *out)
 {
     u64 idx = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 S = (u64)dp.nq * dp.N;
+    const u64 S = (u64)nlimb * dp.N;  // the ciphertext's first nlimb Q limbs
     if (idx >= count * S) return;
     u64 t = idx / S, r = idx % S;
     int l = (int)(r >> dp.log_n);
@@ -296,11 +296,11 @@ dec_combine_kernel(DevParams dp, const u64 *ct, int ncomp, u64 count, const u64 
     out[idx] = v;
 }
 
-int launch_dec_combine(Ctx *c, const u64 *ct, int ncomp, u64 count, u64 *out, hipStream_t s)
+int launch_dec_combine(Ctx *c, const u64 *ct, int ncomp, int nlimb, u64 count, u64 *out, hipStream_t s)
 {
-    u64 total = count * c->nq * c->N;
+    u64 total = count * (u64)nlimb * c->N;
     hipLaunchKernelGGL(dec_combine_kernel, dim3((u32)((total + RNG_THREADS - 1) / RNG_THREADS)), dim3(RNG_THREADS),
-                       0, s, c->dp, ct, ncomp, count, c->sk_ntt, c->sk_ntt_sh, c->sk2_ntt, c->sk2_ntt_sh, out);
+                       0, s, c->dp, ct, ncomp, nlimb, count, c->sk_ntt, c->sk_ntt_sh, c->sk2_ntt, c->sk2_ntt_sh, out);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }

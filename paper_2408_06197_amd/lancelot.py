@@ -53,10 +53,13 @@ _SIGS = {
     "lc_encode": [VP, PD, PD, SZ, _c.c_double, PI64],
     "lc_encode_device": [VP, VP, SZ, SZ, SZ, _c.c_double, VP, VP],
     "lc_decode": [VP, PU64, _c.c_double, PD, PD],
+    "lc_decode_level": [VP, PU64, INT, _c.c_double, PD, PD],
     "lc_crt_to_double": [VP, PU64, SZ, SZ, PD],
     "lc_gaussian_table": [VP, PU64],
     "lc_encrypt": [VP, VP, SZ, U64, U64, VP, VP],
     "lc_decrypt": [VP, VP, INT, SZ, VP, VP],
+    "lc_decrypt_level": [VP, VP, INT, INT, SZ, VP, VP],
+    "lc_rescale": [VP, VP, SZ, INT, INT, VP, VP],
     "lc_ct_sub": [VP, VP, VP, VP, SZ, INT, VP],
     "lc_ct_add": [VP, VP, VP, VP, SZ, INT, VP],
     "lc_ct_mul": [VP, VP, VP, VP, SZ, VP],
@@ -228,6 +231,15 @@ class Context:
                                     im_.ctypes.data_as(PD)))
         return re_ + 1j * im_
 
+    def decode_level(self, residues, scale):
+        """residues [nlimb][N] of the first nlimb Q limbs (coefficient domain)."""
+        r = np.ascontiguousarray(residues, dtype=np.uint64)
+        re_ = np.zeros(self.N // 2)
+        im_ = np.zeros(self.N // 2)
+        self._check(lib().lc_decode_level(self._h, r.ctypes.data_as(PU64), r.shape[0], scale,
+                                          re_.ctypes.data_as(PD), im_.ctypes.data_as(PD)))
+        return re_ + 1j * im_
+
     def crt_to_double(self, residues):
         """residues [nq][ncoeff] -> centred values as float64."""
         r = np.ascontiguousarray(residues, dtype=np.uint64)
@@ -267,6 +279,20 @@ class Context:
         count = ct.numel() // (ncomp * self.nq * self.N)
         out = self.empty(count, self.nq, self.N) if out is None else out
         self._check(lib().lc_decrypt(self._h, _ptr(ct), ncomp, count, _ptr(out), _stream(stream)))
+        return out
+
+    def decrypt_level(self, ct, nlimb, ncomp=2, out=None, stream=None):
+        """ct [count][ncomp][nlimb][N] -> coefficient-domain [count][nlimb][N]."""
+        count = ct.numel() // (ncomp * nlimb * self.N)
+        out = self.empty(count, nlimb, self.N) if out is None else out
+        self._check(lib().lc_decrypt_level(self._h, _ptr(ct), ncomp, nlimb, count, _ptr(out), _stream(stream)))
+        return out
+
+    def rescale(self, ct, nlimb, ncomp=2, out=None, stream=None):
+        """ct [count][ncomp][nlimb][N] (NTT domain) -> [count][ncomp][nlimb - 1][N]."""
+        count = ct.numel() // (ncomp * nlimb * self.N)
+        out = self.empty(count, ncomp, nlimb - 1, self.N) if out is None else out
+        self._check(lib().lc_rescale(self._h, _ptr(ct), count, ncomp, nlimb, _ptr(out), _stream(stream)))
         return out
 
     def ct_sub(self, a, b, out=None, ncomp=2, stream=None):

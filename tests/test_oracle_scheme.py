@@ -290,3 +290,68 @@ def test_masked_sum_exact(oracle_mod, prm):
         decs = [ora.crt(ora.decrypt(cts[i, k], s)) for i in range(n)]
         want = [centered(sum(w[i] * decs[i][t] for i in range(n)), Q) for t in range(N)]
         assert ora.crt(ora.decrypt(agg[k], s)) == want
+
+
+# ---- rescaling (levels of the CKKS Scheme Description) ------------------------
+
+def _residues(ints, mods):
+    return np.array([[v % q for v in ints] for q in mods], dtype=np.uint64)
+
+
+@pytest.mark.parametrize("prm", PARAMS)
+def test_rescale_exact_multiples_and_rounding(oracle_mod, prm):
+    """Closed forms of rounding division: rescaling q_t x + d with |d| < q_t / 2
+    gives x exactly, for every level and integer polynomials x filling most of
+    Q_{t-1} (both signs)."""
+    O = oracle_mod
+    ora = O.Oracle(prm["log_n"], prm["q_bits"], prm["p_bits"])
+    rng = np.random.default_rng(11)
+    N = ora.N
+    for nlimb in range(2, ora.nq + 1):
+        mods = [int(q) for q in ora.q[:nlimb]]
+        qt = mods[-1]
+        Qlow = 1
+        for q in mods[:-1]:
+            Qlow *= q
+        comps = []
+        want = []
+        for comp in range(2):
+            x = [int(rng.integers(-(1 << 62), 1 << 62)) * int(rng.integers(0, 1 << 20)) % Qlow for _ in range(N)]
+            x = [v - Qlow if v > Qlow // 2 else v for v in x]
+            d = [int(rng.integers(-(qt // 2), qt // 2 + 1)) for _ in range(N)]
+            d[0], d[1] = qt // 2, -(qt // 2)  # the extremes of the rounding interval
+            c = [qt * a + b for a, b in zip(x, d)]
+            comps.append(ora.poly_ntt(_residues(c, mods)))
+            want.append(x)
+        ct = np.stack(comps)
+        got = ora.rescale(ct, nlimb)
+        assert got.shape == (2, nlimb - 1, N)
+        for comp in range(2):
+            vals = O.crt_centered(ora.poly_intt(got[comp]), mods[:-1])
+            assert vals == want[comp], (nlimb, comp)
+
+
+def test_rescale_of_encryption_decrypts_to_quotient(oracle_mod):
+    """Encrypt m q_t (scale Delta q_t) and rescale: the decryption at the lower
+    level is m up to (fresh noise) / q_t plus the rounding term (1 + ||s||_1) / 2."""
+    O = oracle_mod
+    ora, s, pk = make(O, log_n=6, q_bits=(45, 40, 40, 40, 40), p_bits=(46, 46))
+    N, t = ora.N, ora.nq - 1
+    qt = int(ora.q[t])
+    rng = np.random.default_rng(4)
+    m = rng.integers(-(1 << 20), 1 << 20, size=N)
+    mq = np.array([int(v) * qt for v in m], dtype=object)
+    # the plaintext m q_t exceeds int64, so encrypt it through its residues
+    pt = ora.poly_ntt(_residues([int(v) for v in mq], ora.q))
+    zero = ora.encrypt(8, 0, np.zeros((1, N), dtype=np.int64), pk)[0]
+    ct = zero.copy()
+    for l, q in enumerate(ora.q):
+        ct[0, l] = [(int(a) + int(b)) % int(q) for a, b in zip(zero[0, l], pt[l])]
+    rs = ora.rescale(ct)
+    sh = ora.signed_to_ntt(s, t)
+    low = [int(q) for q in ora.q[:t]]
+    dec = ora.poly_intt(np.array([[(int(a) + int(b) * int(c)) % q for a, b, c in zip(rs[0, l], rs[1, l], sh[l])]
+                                  for l, q in enumerate(low)], dtype=np.uint64))
+    vals = O.crt_centered(dec, low)
+    bound = 1 + (1 + N) / 2  # noise / q_t < 1, rounding of both components
+    assert max(abs(v - int(x)) for v, x in zip(vals, m)) <= bound
