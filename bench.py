@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
                    help="also run the serving form: ROUNDS Poisson-arriving aggregation rounds")
     p.add_argument("--serve-slots", type=int, default=4)
+    p.add_argument("--sweep-n", dest="sweep_n", action="store_true", default=False,
+                   help="also run the packing-size sweep N = 2^13..2^17 on the depth-3 parameters")
     p.add_argument("--stages", action="store_true", default=True, help="time each stage with events")
     p.add_argument("--no-stages", dest="stages", action="store_false")
     return p.parse_args()
@@ -263,6 +265,73 @@ def cpu_baseline(w, plan, n_cts, min_seconds=12.0):
                       "relinearization and the rotate-and-sum (plan %s) measured whole; %.1f s of oracle time"
                       % (len(pairs), pairs, k, w.n_ct, w.n_ct / k, ",".join(map(str, plan)), spent),
             "seconds_per_pair": sec}
+
+
+def sweep_n(torch, L, synth, log_ns=(13, 14, 15, 16, 17), dim=11_200_000, n=20, steps=2):
+    """Packing-size sweep (a Fig. 3 analog): the paper's default depth-3
+    parameters (Delta = 2^40; Q = 50 + 3 x 40 bits, one 48-bit special prime:
+    218 bits, inside the 128-bit bound at N = 2^13) at N = 2^13 .. 2^17, the
+    same model (n clients x `dim` parameters) packed into N/2 slots per
+    ciphertext.  Per N: device ingest, then the timed round (all pairs'
+    distances with SumDis, the masked sum, decryption), checked against FP64."""
+    res = []
+    for log_n in log_ns:
+        w = synth.Workload(f"depth3_n{1 << log_n}", log_n, (50, 40, 40, 40), (48,), 40, n, dim, 0.005, 4, "scale10",
+                           data_seed=101, crypto_seed=202)
+        N, ln, P = w.N, w.n_ct, w.n_pairs
+        levels = log_n - 1
+        plan = [3] * (levels // 3) + ([levels % 3] if levels % 3 else [])
+        scale = 2.0 ** w.scale_log2
+        t0 = time.perf_counter()
+        kgc = L.Context(log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_KGC)
+        srv = L.Context(log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_SERVER)
+        kgc.keygen(w.crypto_seed)
+        kgc.keygen_rotation(w.crypto_seed, kgc.rotsum_steps(plan))
+        kgc.keys_share(srv)
+        nq = srv.nq
+        cts = torch.empty((n, ln, 2, nq, N), dtype=torch.int64, device="cuda")
+        upd_all = np.empty((n, dim), dtype=np.float64)
+        for i in range(n):
+            upd_all[i] = synth.client_updates(w, clients=[i])[0]
+            z = torch.from_numpy(synth.pack(upd_all[i], w.slots)).cuda()
+            srv.encrypt(srv.encode_device(z, scale), seed=w.crypto_seed + 1, first_object=i * ln, out=cts[i])
+            del z
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        ref = fp64_pair_distances(upd_all)
+        del upd_all
+        dist = torch.empty((P, 2, nq, N), dtype=torch.int64, device="cuda")
+        sumdis = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
+        agg = torch.empty((ln, 2, nq, N), dtype=torch.int64, device="cuda")
+        dec = torch.empty((P, nq, N), dtype=torch.int64, device="cuda")
+        masks = torch.zeros((n, nq, N), dtype=torch.int64, device="cuda")
+        masks[0].fill_(1)
+
+        def step():
+            srv.pairwise_sqdist(cts, plan=plan, sumdis=True, out=dist, sumdis_out=sumdis)
+            srv.masked_sum(cts, masks, out=agg)
+            kgc.decrypt(dist, out=dec)
+
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / steps
+        got = kgc.crt_to_double(dec[:, :, 0].cpu().numpy().view(np.uint64).T.copy()) / scale ** 2
+        rel = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        rec = {"N": N, "ciphertexts_per_client": ln, "plan": plan, "ms_per_round": ms,
+               "distances_per_s": P / (ms / 1e3), "setup_s": t_setup, "max_rel_err_vs_fp64": rel}
+        res.append(rec)
+        log(f"[bench] sweep N=2^{log_n}: {ln} cts/client, plan {','.join(map(str, plan))}: {ms:.1f} ms/round, "
+            f"{P / (ms / 1e3):.1f} distances/s, max rel err {rel:.1e} (setup {t_setup:.1f}s)")
+        del cts, dist, sumdis, agg, dec, masks
+        srv.release_workspace()
+        kgc.release_workspace()
+        del srv, kgc
+        torch.cuda.empty_cache()
+    return res
 
 
 def serve_bench(args, torch, L, srv16, kgc16, plan16):
@@ -738,6 +807,10 @@ def main():
 
     if args.ntt_micro:
         extra["ntt_micro"] = ntt_micro(torch, L)
+        torch.cuda.empty_cache()
+
+    if args.sweep_n:
+        extra["n_sweep"] = sweep_n(torch, L, synth)
         torch.cuda.empty_cache()
 
     if args.serve:

@@ -58,7 +58,7 @@ extern "C" {
 typedef struct lc_ctx lc_ctx;
 
 /* Parameter set (Methods, CKKS Scheme Description: N, Q = prod q_i, special
- * modulus p; hybrid decomposition of Dynamic Hoisting).  log_n in [3, 16];
+ * modulus p; hybrid decomposition of Dynamic Hoisting).  log_n in [3, 17];
  * 1 <= n_q <= 48, 1 <= n_p <= 8; bit sizes in [20, 50]; log_m = 0 means
  * log_n + 1, otherwise log_m >= log_n + 1. */
 typedef struct lc_params {

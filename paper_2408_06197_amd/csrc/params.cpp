@@ -132,7 +132,7 @@ static const T *upload(Ctx *c, const std::vector<T> &h)
 int build_params(Ctx *c, const lc_params *prm)
 {
     if (!prm) return fail(c, LC_EINVAL, "params is NULL");
-    if (prm->log_n < 3 || prm->log_n > 16) return fail(c, LC_EUNSUP, "log_n must lie in [3, 16]");
+    if (prm->log_n < 3 || prm->log_n > 17) return fail(c, LC_EUNSUP, "log_n must lie in [3, 17]");
     if (prm->n_q < 1 || prm->n_q > 48 || prm->n_p < 1 || prm->n_p > MAX_NP)
         return fail(c, LC_EUNSUP, "need 1 <= n_q <= 48 and 1 <= n_p <= 8");
     if (!prm->q_bits || !prm->p_bits) return fail(c, LC_EINVAL, "bit-size arrays are NULL");

@@ -56,7 +56,7 @@ CFG1 = (synth.CFG1.log_n, synth.CFG1.q_bits, synth.CFG1.p_bits)
 
 # ---- NTT ---------------------------------------------------------------------
 
-@pytest.mark.parametrize("log_n", [3, 4, 5, 8, 11, 12, 13, 14, 15, 16])
+@pytest.mark.parametrize("log_n", [3, 4, 5, 8, 11, 12, 13, 14, 15, 16, 17])
 def test_ntt_bitexact(torch, L, oracle_mod, log_n):
     O = oracle_mod
     qb, pb = (50, 50, 40), (50, 45)
@@ -361,6 +361,24 @@ def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
         got = down(g)
         for c in range(2):
             assert np.array_equal(got[c], want[c]), (cmin, cts_per_wg, fold, one, c)
+
+
+def test_rotate_sum_n17_depth3(torch, L, oracle_mod):
+    """N = 2^17 (the top of the packing-size sweep) on the depth-3 parameters:
+    transforms outside the two-pass range and the key switch's unfused
+    conversions, the 3,3,3,3,3,1 plan (cycle walks, short cycles and a single
+    rotation); one ciphertext against the oracle."""
+    O = oracle_mod
+    prm = (17, (50, 40, 40, 40), (48,))
+    plan = [3, 3, 3, 3, 3, 1]
+    ora0 = O.Oracle(*prm)
+    steps = ora0.rotsum_steps(plan)
+    ctx, ora, keys = make_pair(L, O, *prm, seed=29, steps=steps)
+    cts = synth.uniform_residues(31, ctx.q, (1, 2, ctx.N))
+    want = ora.rotate_sum(cts[0], plan, [keys["rot"][k] for k in steps])
+    g = up(torch, cts)
+    ctx.rotate_sum(g, plan)
+    assert np.array_equal(down(g)[0], want)
 
 
 # ---- the pairwise pipeline -----------------------------------------------------------

@@ -108,7 +108,7 @@ def test_crt_small_values_long_chain(L, oracle_mod):
 
 def test_argument_errors(L):
     with pytest.raises(L.LancelotError) as e:
-        L.Context(17, (50,), (50,), device=-1)
+        L.Context(18, (50,), (50,), device=-1)
     assert e.value.code == L.LC_EUNSUP
     with pytest.raises(L.LancelotError) as e:
         L.Context(12, (55,), (50,), device=-1)
