@@ -512,10 +512,16 @@ def main():
                 tuned.setdefault("pair_kernel_ms", {})["%dx%d" % (lanes, ppt)] = ms
                 if best is None or ms < best[0]:
                     best = (ms, lanes, ppt)
-        del trip
         srv.set_tuning("pair_lanes", best[1])
         srv.set_tuning("pair_ppt", best[2])
         tuned["pair_lanes"], tuned["pair_ppt"] = best[1], best[2]
+        # the Gram form on the int8 matrix cores (4 coefficients per workgroup)
+        srv.set_tuning("pair_mfma", 4)
+        ms = event_time(torch, lambda: srv.pair_triples(cts, out=trip))
+        tuned["pair_kernel_ms"]["gram_mfma_4"] = ms
+        tuned["pair_mfma"] = 4 if ms < best[0] else 0
+        srv.set_tuning("pair_mfma", tuned["pair_mfma"])
+        del trip
         # hoisting plan jointly with the shortest tile cycle that the
         # cycle-walking inner product takes (2^30: never)
         bestp = None
@@ -777,19 +783,27 @@ def main():
         limb_ntts_per_ks = nq + srv.dnum * nq + 2 * srv.np + 2 * nq  # (L+1+K-alpha) = L+1 as alpha = K
         ntt_ms_step = ks_count * limb_ntts_per_ks * nt["transform_ms_per_limb_poly"]
         updates = P * ln * nq * N
-        a2 = {"bound": "alu", "achieved": A2_OPS_PER_UPDATE * updates / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e12,
-              "peak": VALU_PEAK_TOPS, "unit": "T FP64 lane-ops/s", "traffic": None, "kernel": "pair_triples_kernel",
-              "units_per_launch": "%d updates x %d FP64 lane-ops" % (updates, A2_OPS_PER_UPDATE),
-              "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
+        a2_bytes = n * ln * 2 * nq * N * 8 + P * 3 * nq * N * 8
+        if tuned.get("pair_mfma"):  # the Gram form: HBM-bound by design (ciphertexts read once)
+            a2 = {"bound": "hbm", "achieved": a2_bytes / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e9,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "kernel": "pair_gram_kernel",
+                  "units_per_launch": "%d bytes of ciphertexts in and triples out" % a2_bytes,
+                  "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
+        else:
+            a2 = {"bound": "alu",
+                  "achieved": A2_OPS_PER_UPDATE * updates / (extra["stage_ms"]["pair_triples"] / 1e3) / 1e12,
+                  "peak": VALU_PEAK_TOPS, "unit": "T FP64 lane-ops/s", "traffic": None, "kernel": "pair_triples_kernel",
+                  "units_per_launch": "%d updates x %d FP64 lane-ops" % (updates, A2_OPS_PER_UPDATE),
+                  "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
         ntt = {"bound": "hbm", "achieved": nt["bytes_per_launch"] / (nt["launch_ms"] / 1e3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "kernel": "ntt_fast_kernel",
                "units_per_launch": "%d limb-polys x 8N bytes" % nt["limb_polys"], "launch_ms": nt["launch_ms"],
                "est_ms_per_step": ntt_ms_step}
         for r in (a2, ntt):
             r["frac"] = r["achieved"] / r["peak"]
-        if A2_PMC["source_sha256"] == _a2_source_sha256():
+        if not tuned.get("pair_mfma") and A2_PMC["source_sha256"] == _a2_source_sha256():
             a2["traffic"] = A2_PMC["fetch_bytes"] + A2_PMC["write_bytes"]
-            a2["traffic_vs_algorithmic"] = a2["traffic"] / (n * ln * 2 * nq * N * 8 + P * 3 * nq * N * 8)
+            a2["traffic_vs_algorithmic"] = a2["traffic"] / a2_bytes
         # the pair-triple kernel is the step's largest single kernel (one
         # launch); the NTT's share is spread over hundreds of launches
         roof = a2

@@ -263,7 +263,10 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
 
 /* Launch-shape tuning, results unchanged (every shape computes the same
  * residues): "pair_lanes" (8/16/32/64 coefficients per workgroup of the pair
- * kernel), "pair_ppt" (1/3/4/6 pairs per lane), "ks_chunk" (1..256
+ * kernel), "pair_ppt" (1/3/4/6 pairs per lane), "pair_mfma" (0 = per-pair
+ * kernel; 4 or 2 = for n <= 24 clients the triples are read off exact
+ * modular Gram products of the 2n (client, component) rows on the int8
+ * matrix cores, 4 or 2 coefficients per workgroup), "ks_chunk" (1..256
  * ciphertexts per key-switch batch), "ntt_sub_kb" (0..4194304: two-pass NTTs
  * run both passes per sub-batch of about this many KiB; 0 = whole batch),
  * "mac_cts" (8/16 ciphertexts per lane of the key-switch inner product),

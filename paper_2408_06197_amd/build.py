@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblancelot.so")
 
-HIP_SOURCES = ["api.hip", "ntt.hip", "ops.hip", "keyswitch.hip", "rng.hip", "encode_dev.hip", "rescale.hip", "params.cpp", "encode.cpp"]
+HIP_SOURCES = ["api.hip", "ntt.hip", "ops.hip", "keyswitch.hip", "rng.hip", "encode_dev.hip", "rescale.hip", "pair_gram.hip", "params.cpp", "encode.cpp"]
 CXX_SOURCES = ["cdt.cpp"]  # binary128 arithmetic: built with g++ and libquadmath
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

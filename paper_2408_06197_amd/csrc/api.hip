@@ -781,6 +781,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     if (k == "pair_lanes") {
         if (value != 8 && value != 16 && value != 32 && value != 64) return fail(c, LC_EINVAL, "pair_lanes: 8/16/32/64");
         c->tune.pair_lanes = value;
+    } else if (k == "pair_mfma") {
+        if (value != 0 && value != 2 && value != 4) return fail(c, LC_EINVAL, "pair_mfma: 0/2/4");
+        c->tune.pair_mfma = value;
     } else if (k == "pair_ppt") {
         if (value != 1 && value != 3 && value != 4 && value != 6) return fail(c, LC_EINVAL, "pair_ppt: 1/3/4/6");
         c->tune.pair_ppt = value;

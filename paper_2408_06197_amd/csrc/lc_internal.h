@@ -109,6 +109,7 @@ struct Ctx {
     struct Tuning {
         int pair_lanes = 16;  // coefficients per workgroup of the pair-triple kernel
         int pair_ppt = 4;     // pairs per lane (1, 3, 4 or 6)
+        int pair_mfma = 0;    // Gram form on the int8 MFMA with 4 or 2 coefficients per workgroup (0: per-pair form)
         int ks_chunk = 64;    // ciphertexts per key-switch batch
         int ntt_sub_kb = 0;   // two-pass NTTs run per sub-batch of this many KiB (0: whole batch)
         int mac_cts = 8;      // ciphertexts per lane of the key-switch inner product (8 or 16)
@@ -215,6 +216,9 @@ int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, 
 // at cts + i row_len 2 S (row_len >= len packed ciphertexts)
 int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, const u64 *masks, u64 *trip,
                         hipStream_t s);
+int pair_gram_positions(Ctx *c, int n, int want);
+int launch_pair_gram(Ctx *c, int pm, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2,
+                     u64 d2_stride, int accumulate, hipStream_t s);
 int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
                         int accumulate, hipStream_t s);
 int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s);

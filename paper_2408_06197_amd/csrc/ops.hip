@@ -520,6 +520,10 @@ int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d0
 {
     if (n < 2 || n > PT_MAXN) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
     if (len < 1) return fail(c, LC_EINVAL, "len must be >= 1");
+    if (c->tune.pair_mfma) {  // the Gram form on the matrix cores, where its LDS fits
+        const int pm = pair_gram_positions(c, n, c->tune.pair_mfma);
+        if (pm) return launch_pair_gram(c, pm, cts, n, len, d01, d01_stride, d2, d2_stride, accumulate, s);
+    }
     int P = n * (n - 1) / 2;
     int ppt = c->tune.pair_ppt;
     if (P <= 64) ppt = 1;  // few pairs: one per lane

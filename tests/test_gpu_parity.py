@@ -461,6 +461,7 @@ def test_pair_tuning_shapes_bitexact(torch, L, oracle_mod, lanes, ppt):
     ora = O.Oracle(*prm)
     n, ln = 13, 6
     cts = synth.uniform_residues(77, ctx.q, (n, ln, 2, ctx.N))
+    ctx.set_tuning("pair_mfma", 0)  # the per-pair kernel's shapes
     ctx.set_tuning("pair_lanes", lanes)
     ctx.set_tuning("pair_ppt", ppt)
     got = down(ctx.pair_triples(up(torch, cts)))
@@ -513,7 +514,7 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
 
 def test_set_tuning_rejects_bad_values(L):
     ctx = L.Context(5, (30, 28, 28), (30,), device=0)
-    for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
+    for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("pair_mfma", 3), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
                         ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
                         ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("mac_cycle_short", 2), ("mac_short_cts", 4),
                         ("nope", 1)):
