@@ -257,15 +257,29 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
 #pragma unroll
         for (int i = 0; i < 16; i++) v[i] = reduce_d(v[i], q, qinv);
     } else {
+        // all eight loads are issued before any value is used: a conversion
+        // between them would make each load wait for the one before
+        ulonglong2 p2[8];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
             u32 e = 2 * (tid + (u32)i * nthreads);
             u64 g;
             if (BLOCKS) g = ((u64)tile * cols + (e >> LOG_S)) * S + (e & (S - 1));
             else g = (hi_col * S + e / (u32)cols) * stride + lo0 + e % (u32)cols;
-            ulonglong2 p2 = *reinterpret_cast<const ulonglong2 *>(src + g);
-            v[2 * i] = first_ ? u64_to_d(p2.x) : __longlong_as_double((long long)p2.x);
-            v[2 * i + 1] = first_ ? u64_to_d(p2.y) : __longlong_as_double((long long)p2.y);
+            p2[i] = *reinterpret_cast<const ulonglong2 *>(src + g);
+        }
+        if (first_) {
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                v[2 * i] = u64_to_d(p2[i].x);
+                v[2 * i + 1] = u64_to_d(p2[i].y);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                v[2 * i] = __longlong_as_double((long long)p2[i].x);
+                v[2 * i + 1] = __longlong_as_double((long long)p2[i].y);
+            }
         }
     }
 #pragma unroll

@@ -139,42 +139,48 @@ masked_sum_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, con
     for (int t = 0; t < ROWS; t++)
 #pragma unroll
         for (int e = 0; e < COEF; e++) acc[t][e] = 0.0;
+    // Every load is unconditional, from a clamped client and row: a load
+    // under a condition makes the wave wait for all loads in flight where
+    // the branches join.  A client past n gets mask 0, so its (re-read)
+    // ciphertext adds nothing; rows past the end are computed, not stored.
     for (int i0 = 0; i0 < n; i0 += 8) {
         double m[8][COEF];
+        const u64 *cbase[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) {
+            const int iu = min(i0 + u, n - 1);
+            const bool live = i0 + u < n;
+            cbase[u] = cts + (u64)iu * client_stride + r;
             if (COEF == 2) {
-                ulonglong2 v = i0 + u < n ? *reinterpret_cast<const ulonglong2 *>(masks + (u64)(i0 + u) * S + r)
-                                          : ulonglong2{0, 0};
-                m[u][0] = u64_to_d(v.x);
-                m[u][COEF - 1] = u64_to_d(v.y);
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(masks + (u64)iu * S + r);
+                m[u][0] = live ? u64_to_d(v.x) : 0.0;
+                m[u][COEF - 1] = live ? u64_to_d(v.y) : 0.0;
             } else {
-                m[u][0] = i0 + u < n ? u64_to_d(masks[(u64)(i0 + u) * S + r]) : 0.0;
+                const u64 v = masks[(u64)iu * S + r];
+                m[u][0] = live ? u64_to_d(v) : 0.0;
             }
         }
-        const u64 *base = cts + (u64)i0 * client_stride + (u64)row0 * S + r;
 #pragma unroll
         for (int t = 0; t < ROWS; t++) {
-            if (row0 + t < rows) {
-                double c[8][COEF];
+            const u64 rt = (u64)min(row0 + t, rows - 1);
+            double c[8][COEF];
 #pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const u64 *src = base + (u64)u * client_stride + (u64)t * S;
-                    if (COEF == 2) {
-                        ulonglong2 v = i0 + u < n ? *reinterpret_cast<const ulonglong2 *>(src) : ulonglong2{0, 0};
-                        c[u][0] = u64_to_d(v.x);
-                        c[u][COEF - 1] = u64_to_d(v.y);
-                    } else {
-                        c[u][0] = i0 + u < n ? u64_to_d(*src) : 0.0;
-                    }
+            for (int u = 0; u < 8; u++) {
+                const u64 *src = cbase[u] + rt * S;
+                if (COEF == 2) {
+                    const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(src);
+                    c[u][0] = u64_to_d(v.x);
+                    c[u][COEF - 1] = u64_to_d(v.y);
+                } else {
+                    c[u][0] = u64_to_d(*src);
                 }
+            }
 #pragma unroll
-                for (int u = 0; u < 8; u++) {
+            for (int u = 0; u < 8; u++) {
 #pragma unroll
-                    for (int e = 0; e < COEF; e++) {
-                        acc[t][e] += mulmod_d(c[u][e], m[u][e], q, qinv);
-                        if (u == 3 || u == 7) acc[t][e] = reduce_d(acc[t][e], q, qinv);
-                    }
+                for (int e = 0; e < COEF; e++) {
+                    acc[t][e] += mulmod_d(c[u][e], m[u][e], q, qinv);
+                    if (u == 3 || u == 7) acc[t][e] = reduce_d(acc[t][e], q, qinv);
                 }
             }
         }
