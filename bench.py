@@ -38,7 +38,7 @@ A2_OPS_PER_UPDATE = 23
 # profiles/pair_triples_n65536_l24_20clients_pmc.txt.  Valid only for the
 # kernel source it was taken on: the section of ops.hip is hashed at run time.
 A2_PMC = {"fetch_bytes": 2.0 * 84056231 * 1024, "write_bytes": 7004160 * 1024,
-          "source_sha256": "053a07d31ef910cd5ac1422ddbc85a697023e6b45c1d6a7808d08eaca5695de2"}
+          "source_sha256": "2922c9900c02ddf658ce4917553015c79efdfb4ab2f23ce688a97d7ba92298fd"}
 
 
 def _a2_source_sha256():
