@@ -153,13 +153,24 @@ __device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 
             u32 a1 = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
             double w = tw[base + (a1 >> (LOG_S - sl))];
             double X = x[h], Y = x[h | (1 << hb)];
-            // invariant: |X|, |Y| <= 2q on entry and exit
             if (!INVERSE) {
-                double T = mulmod_d(Y, w, q, qinv);  // |T| <= 2q
-                X = reduce_d(X, q, qinv);            // |X| <= q/2 + 1
+                // X is reduced only on every other stage, counted back from
+                // the pass's last one (which always reduces).  With q < 2^50
+                // the Barrett estimate of T = Y w mod q is off by at most
+                // 1/2 + 3 |Y| 2^-53 <= 1/2 + 0.375 |Y| / q, so |T| <= (1/2 +
+                // 0.375 b) q for |Y| <= b q.  A lazy stage takes entries
+                // <= 2.46 q to <= 1.375 * 2.46 q + q/2 <= 3.89 q, a reducing
+                // stage takes those back to <= q/2 + 1 + (1/2 + 0.375 * 3.89) q
+                // <= 2.46 q: every mulmod input stays below 4 q and every value
+                // below 2^52, so all of it is exact.  Pass inputs (canonical, or
+                // a reduced conversion sum) and outputs (after a reducing
+                // stage) lie within 2.46 q.
+                double T = mulmod_d(Y, w, q, qinv);
+                if (((LOG_S - 1 - sl) & 1) == 0) X = reduce_d(X, q, qinv);  // |X| <= q/2 + 1
                 x[h] = X + T;
                 x[h | (1 << hb)] = X - T;
             } else {
+                // invariant: |X|, |Y| <= 2q on entry and exit
                 double S = reduce_d(X + Y, q, qinv);
                 x[h | (1 << hb)] = mulmod_d(X - Y, w, q, qinv);
                 x[h] = S;
