@@ -12,8 +12,8 @@
  * every transform is a textbook one.  No Montgomery, Barrett or Shoup form
  * appears here on purpose.
  *
- * Conventions (readings of places where the paper is silent are listed in
- * the design doc and repeated next to each function):
+ * Conventions (readings of places where the paper is silent are stated next
+ * to each function):
  *   - Residues are canonical, in [0, q).
  *   - A polynomial over the RNS basis is laid out limb-major: [limb][N].
  *   - A ciphertext is [comp][limb][N], kept in the NTT domain (double-CRT,
@@ -23,9 +23,10 @@
  *
  * Parity status: every function here is pinned by tests/test_oracle_*.py
  * against brute force, closed forms, library routines or invariants, except
- * the bit patterns that follow from this build's own conventions (PRNG stream
- * layout, gadget, fast base conversion, rotate-sum plan); those are "parity
- * unpinned" beyond the invariants listed in the design doc.
+ * the bit patterns that follow from conventions the paper leaves open (PRNG
+ * stream layout, gadget, fast base conversion, rotate-sum plan); those are
+ * "parity unpinned" beyond the invariants their tests check (decryption,
+ * linearity, agreement with the exact integer computation within the noise).
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -1,8 +1,7 @@
 """Pins of the oracle's modular arithmetic, primes and NTT roots.
 
 Each check compares against something other than the oracle: Python's big
-integers, sympy's primality test and primitive roots, or values the survey of
-the parameter rule computed independently.
+integers, or sympy's primality test and primitive roots.
 """
 import random
 
@@ -101,13 +100,30 @@ def test_find_primes(oracle_mod, log_m, bits):
         assert q.bit_length() == b and (q - 1) % (1 << log_m) == 0
 
 
-def test_find_primes_survey_values(oracle_mod):
-    # Values printed for the N=2^12 chain (M = 2^13): the first two 40-bit and
-    # the first two 30-bit primes of the rule.
+def _rule_primes_sympy(log_m, b, count):
+    """The first `count` primes q = k M + 1 < 2^b (M = 2^log_m), largest k
+    first, found with sympy's primality test."""
+    M = 1 << log_m
+    out, k = [], ((1 << b) - 1) // M
+    while len(out) < count:
+        c = k * M + 1
+        assert c >= 1 << (b - 1)
+        if sympy.isprime(c):
+            out.append(c)
+        k -= 1
+    return out
+
+
+def test_find_primes_n4096_chain(oracle_mod):
+    # The N=2^12 chain (M = 2^13): the first two 40-bit and the first two
+    # 30-bit primes of the rule, found independently with sympy; mixed bit
+    # sizes take the next unused prime of each size.
     O = oracle_mod
-    assert O.find_primes(13, [40, 40]) == [1099511480321, 1099511390209]
-    assert O.find_primes(13, [30, 30]) == [1073692673, 1073668097]
-    assert O.find_primes(13, [40, 30, 30, 40]) == [1099511480321, 1073692673, 1073668097, 1099511390209]
+    p40, p30 = _rule_primes_sympy(13, 40, 2), _rule_primes_sympy(13, 30, 2)
+    assert p40 == [1099511480321, 1099511390209] and p30 == [1073692673, 1073668097]
+    assert O.find_primes(13, [40, 40]) == p40
+    assert O.find_primes(13, [30, 30]) == p30
+    assert O.find_primes(13, [40, 30, 30, 40]) == [p40[0], p30[0], p30[1], p40[1]]
 
 
 @pytest.mark.parametrize("q,log_n", [(7681, 8), (12289, 9), (12289, 10), (97, 4), (17, 3)])
