@@ -109,3 +109,25 @@ def test_pair_gram_extreme_digits(torch, L, oracle_mod, pattern):
     ctx.set_tuning("pair_mfma", 4)
     got = down(ctx.pair_triples(up(torch, cts)))
     check_all(got, ora, cts)
+
+
+def test_pair_gram_full_shape(torch, L, oracle_mod):
+    """The N = 2^16, 24-limb shape of the benchmark workload with 20 clients
+    (3 row blocks, the XCD remap over 16384 workgroups per limb) and a ragged
+    70-ciphertext row: equal to the per-pair kernel bit for bit, and sampled
+    pairs (first, middle, last) equal to the oracle."""
+    O = oracle_mod
+    prm = (16, (50,) * 24, (50,) * 4)
+    ctx = L.Context(*prm, device=0)
+    ora = O.Oracle(*prm)
+    n, ln = 20, 70
+    cts = synth.uniform_residues(777, ctx.q, (n, ln, 2, ctx.N))
+    g = up(torch, cts)
+    ctx.set_tuning("pair_mfma", 4)
+    got = ctx.pair_triples(g)
+    ctx.set_tuning("pair_mfma", 0)
+    ref = ctx.pair_triples(g)
+    assert torch.equal(got, ref)
+    got = down(got)
+    for p, (i, j) in ((0, (0, 1)), (98, (5, 19)), (189, (18, 19))):
+        assert np.array_equal(got[p], ora.pair_triple(cts, i, j)), (i, j)
