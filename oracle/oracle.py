@@ -358,6 +358,26 @@ def crt_centered(residues, moduli, coeffs=None):
 # Parameter set and scheme operations
 # --------------------------------------------------------------------------
 
+def pair_triple_columns(xi, xj, q) -> np.ndarray:
+    """One client pair's tensor-squared differences summed over the packed
+    ciphertexts (Methods, Computing the Pairwise Distances: the squared
+    difference as a ciphertext-ciphertext product, relinearized once after the
+    sum as in Methods, Lazy Relinearization), from the definition, on residue
+    columns.  xi, xj: [LEN][2][m] residues of one limb (modulus q) of clients
+    i and j at m coefficient positions, in the NTT domain where the tensor
+    product is pointwise.  Returns [3][m]: sum_k d0^2, 2 sum_k d0 d1 and
+    sum_k d1^2 mod q, with (d0, d1) = ct_i[k] - ct_j[k], in Python integers."""
+    q = int(q)
+    a = np.asarray(xi, dtype=np.uint64).astype(object)
+    b = np.asarray(xj, dtype=np.uint64).astype(object)
+    d0, d1 = a[:, 0, :] - b[:, 0, :], a[:, 1, :] - b[:, 1, :]
+    out = np.empty((3, a.shape[2]), dtype=np.uint64)
+    out[0] = [int(v) % q for v in (d0 * d0).sum(axis=0)]
+    out[1] = [(2 * int(v)) % q for v in (d0 * d1).sum(axis=0)]
+    out[2] = [int(v) % q for v in (d1 * d1).sum(axis=0)]
+    return out
+
+
 class Oracle:
     """One RNS-CKKS parameter set: N = 2^log_n, q_0..q_L then p_0..p_{K-1},
     digit size alpha = K, dnum = ceil((L+1)/alpha)."""

@@ -119,3 +119,15 @@ def small_workload(log_n=5, q_bits=(30, 28, 28), p_bits=(30,), n_clients=4, dim=
     """A tiny workload for fast CPU tests (parity at several tiles needs larger N)."""
     return Workload(name, log_n, tuple(q_bits), tuple(p_bits), scale_log2, n_clients, dim, 0.01, 1, "scale10",
                     data_seed=77, crypto_seed=88)
+
+
+def device_residues(torch, rng_seed: int, bits: int, shape):
+    """Uniform integers in [0, 2^bits) generated on the GPU from a seeded
+    torch generator (int64 storage).  With bits <= 49 they are canonical
+    residues of every prime of 50 bits, so full-size inputs never cross the
+    host."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(rng_seed)
+    t = torch.empty(tuple(shape), dtype=torch.int64, device="cuda")
+    t.random_(0, 1 << bits, generator=g)
+    return t

@@ -99,3 +99,24 @@ def test_permutation_mask_example(oracle_mod):
     want = np.zeros((5, 5), dtype=np.int64)
     want[0, 0] = want[1, 2] = want[2, 4] = 1
     assert np.array_equal(P, want)
+
+
+def test_pair_triple_columns_pins(oracle_mod):
+    """The column form of the pair triple equals the C oracle's full-array
+    pair triple on every limb and coefficient (two implementations, Python
+    integers and 128-bit C), and a closed form: constant ciphertexts give
+    LEN (a - b)^2 in each slot of the triple."""
+    O = oracle_mod
+    ora = O.Oracle(5, (50, 45, 40), (50,))
+    cts = synth.uniform_residues(91, ora.q, (3, 7, 2, 32))
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        full = ora.pair_triple(cts, i, j)
+        for l, q in enumerate(ora.q):
+            got = O.pair_triple_columns(cts[i, :, :, l, :], cts[j, :, :, l, :], q)
+            assert np.array_equal(got, full[:, l, :]), (i, j, l)
+    q = int(ora.q[0])
+    a = np.zeros((5, 2, 1), dtype=np.uint64)
+    b = np.zeros((5, 2, 1), dtype=np.uint64)
+    a[:, 0], a[:, 1], b[:, 0], b[:, 1] = 7, q - 3, q - 1, 5  # d0 = 8 - q = 8, d1 = q - 8 = -8 (mod q)
+    got = O.pair_triple_columns(a, b, q)
+    assert [int(v) for v in got[:, 0]] == [5 * 64 % q, (2 * 5 * -64) % q, 5 * 64 % q]
