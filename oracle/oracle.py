@@ -378,6 +378,21 @@ def pair_triple_columns(xi, xj, q) -> np.ndarray:
     return out
 
 
+def masked_sum_columns(cols, masks, q) -> np.ndarray:
+    """The server's plaintext-mask aggregate (Algorithm 1: the mask products
+    summed over clients, Methods, Masked-Based Encrypted Sorting), from the
+    definition, on residue columns: cols [n][LEN][2][m] residues of one limb
+    (modulus q) of every client's packed ciphertexts at m coefficient
+    positions, masks [n][m] the clients' mask plaintexts there, both in the
+    NTT domain where the plaintext product is pointwise.  Returns
+    [LEN][2][m]: sum_i cols[i] * masks[i] mod q, in Python integers."""
+    q = int(q)
+    c = np.asarray(cols, dtype=np.uint64).astype(object)
+    w = np.asarray(masks, dtype=np.uint64).astype(object)
+    acc = (c * w[:, None, None, :]).sum(axis=0)
+    return np.vectorize(lambda v: int(v) % q, otypes=[object])(acc).astype(np.uint64)
+
+
 class Oracle:
     """One RNS-CKKS parameter set: N = 2^log_n, q_0..q_L then p_0..p_{K-1},
     digit size alpha = K, dnum = ceil((L+1)/alpha)."""

@@ -1,9 +1,12 @@
-"""Parity of the pair kernel (a2) at the benchmark workload's full size:
-N = 2^16, 24 limbs, 20 clients x 342 packed ciphertexts (172 GB of
-ciphertexts resident in HBM), in the launch shape the bench times.  The
-oracle computes sampled outputs one by one from their definition on the same
-residues: the first, a middle and the last pair, at three limbs and three
-windows of 32 coefficients (the range's start, middle and end)."""
+"""Parity at the benchmark workload's full size: N = 2^16, 24 limbs, 20 clients
+x 342 packed ciphertexts (172 GB resident in HBM, generated on the GPU from a
+seeded generator), in the launch shapes the bench times.  The oracle computes
+sampled outputs one by one from their definitions on the same residues, at
+three limbs and three windows of 32 coefficients (the range's start, middle
+and end):
+  * the pair kernel (a2): the first, a middle and the last pair;
+  * the plaintext-mask aggregate (a6): every packed ciphertext and component.
+"""
 import gc
 
 import numpy as np
@@ -12,6 +15,13 @@ import pytest
 import synth
 
 pytestmark = pytest.mark.gpu
+
+LOG_N, NQ, N_CLIENTS, LEN = 16, 24, 20, 342
+SAMPLE_LIMBS = (0, 11, 23)
+
+
+def windows(N):
+    return (0, N // 2 - 16, N - 32)
 
 
 @pytest.fixture(scope="module")
@@ -28,15 +38,22 @@ def L():
     return lancelot
 
 
-def test_pair_triples_full_size_sampled(torch, L, oracle_mod):
-    O = oracle_mod
-    log_n, nq = 16, 24
-    ctx = L.Context(log_n, (50,) * nq, (50,) * 4, device=0)
+@pytest.fixture(scope="module")
+def full(torch, L):
+    ctx = L.Context(LOG_N, (50,) * NQ, (50,) * 4, device=0)
     assert all(int(q) > 1 << 49 for q in ctx.q)  # 49-bit inputs are canonical for every limb
     gc.collect()
     torch.cuda.empty_cache()
-    n, ln, N = 20, 342, 1 << log_n
-    cts = synth.device_residues(torch, 4242, 49, (n, ln, 2, nq, N))
+    cts = synth.device_residues(torch, 4242, 49, (N_CLIENTS, LEN, 2, NQ, 1 << LOG_N))
+    yield ctx, cts
+    del cts
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_pair_triples_full_size_sampled(torch, oracle_mod, full):
+    O = oracle_mod
+    ctx, cts = full
     ctx.set_tuning("pair_mfma", 0)
     ctx.set_tuning("pair_lanes", 16)
     ctx.set_tuning("pair_ppt", 4)
@@ -44,14 +61,32 @@ def test_pair_triples_full_size_sampled(torch, L, oracle_mod):
     torch.cuda.synchronize()
     pairs = {0: (0, 1), 98: (5, 19), 189: (18, 19)}
     try:
-        for l in (0, 11, 23):
-            for c0 in (0, N // 2 - 16, N - 32):
-                cols = cts[:, :, :, l, c0:c0 + 32].cpu().numpy().view(np.uint64)  # [n][ln][2][32]
+        for l in SAMPLE_LIMBS:
+            for c0 in windows(ctx.N):
+                cols = cts[:, :, :, l, c0:c0 + 32].cpu().numpy().view(np.uint64)  # [n][LEN][2][32]
                 got = trip[:, :, l, c0:c0 + 32].cpu().numpy().view(np.uint64)    # [P][3][32]
                 for p, (i, j) in pairs.items():
                     want = O.pair_triple_columns(cols[i], cols[j], ctx.q[l])
                     assert np.array_equal(got[p], want), (p, l, c0)
     finally:
-        del cts, trip
-        gc.collect()
+        del trip
+        torch.cuda.empty_cache()
+
+
+def test_masked_sum_full_size_sampled(torch, oracle_mod, full):
+    O = oracle_mod
+    ctx, cts = full
+    masks = synth.device_residues(torch, 4343, 49, (N_CLIENTS, NQ, ctx.N))
+    ctx.set_tuning("ms_shape", 2)
+    out = ctx.masked_sum(cts, masks)
+    torch.cuda.synchronize()
+    try:
+        for l in SAMPLE_LIMBS:
+            for c0 in windows(ctx.N):
+                cols = cts[:, :, :, l, c0:c0 + 32].cpu().numpy().view(np.uint64)
+                w = masks[:, l, c0:c0 + 32].cpu().numpy().view(np.uint64)
+                got = out[:, :, l, c0:c0 + 32].cpu().numpy().view(np.uint64)  # [LEN][2][32]
+                assert np.array_equal(got, O.masked_sum_columns(cols, w, ctx.q[l])), (l, c0)
+    finally:
+        del out, masks
         torch.cuda.empty_cache()

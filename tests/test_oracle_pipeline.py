@@ -120,3 +120,21 @@ def test_pair_triple_columns_pins(oracle_mod):
     a[:, 0], a[:, 1], b[:, 0], b[:, 1] = 7, q - 3, q - 1, 5  # d0 = 8 - q = 8, d1 = q - 8 = -8 (mod q)
     got = O.pair_triple_columns(a, b, q)
     assert [int(v) for v in got[:, 0]] == [5 * 64 % q, (2 * 5 * -64) % q, 5 * 64 % q]
+
+
+def test_masked_sum_columns_pins(oracle_mod):
+    """The column form of the masked sum equals the C oracle's full-array
+    masked sum on every limb and coefficient, and one-hot masks select one
+    client's ciphertexts."""
+    O = oracle_mod
+    ora = O.Oracle(5, (50, 45, 40), (50,))
+    n, ln = 5, 3
+    cts = synth.uniform_residues(92, ora.q, (n, ln, 2, 32))
+    masks = synth.uniform_residues(93, ora.q, (n, 32))
+    full = ora.masked_sum(cts, masks)
+    for l, q in enumerate(ora.q):
+        got = O.masked_sum_columns(cts[:, :, :, l, :], masks[:, l, :], q)
+        assert np.array_equal(got, full[:, :, l, :]), l
+    hot = np.zeros((n, 32), dtype=np.uint64)
+    hot[3] = 1
+    assert np.array_equal(O.masked_sum_columns(cts[:, :, :, 0, :], hot, ora.q[0]), cts[3, :, :, 0, :])
