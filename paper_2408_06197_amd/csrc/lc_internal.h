@@ -104,6 +104,7 @@ struct Ctx {
     void *enc_w = nullptr, *enc_twist = nullptr;
     int *enc_slot = nullptr;
     size_t ws_limit = 0;
+    size_t gram_lds_allowed[2] = {0, 0};  // dynamic LDS granted to the Gram-form pair kernel (2 / 4 coefficients)
 
     // launch-shape tuning (lc_set_tuning)
     struct Tuning {

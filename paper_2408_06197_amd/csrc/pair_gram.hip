@@ -292,11 +292,12 @@ static int launch_pg(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_s
     const int R = 2 * n, nrb = (R + 15) / 16, ntile = nrb * (nrb + 1) / 2;
     const int nwaves = (PM * ntile + PG_IPW - 1) / PG_IPW;
     const size_t lds = SH::lds_bytes(R);
-    static size_t attr_bytes = 0;  // dynamic LDS allowed so far (beyond 64 KiB it must be asked for)
-    if (lds > attr_bytes) {
+    // dynamic LDS beyond 64 KiB must be asked for; tracked per context (one device)
+    size_t &allowed = c->gram_lds_allowed[PM == 4 ? 1 : 0];
+    if (lds > allowed) {
         LC_HIP(c, hipFuncSetAttribute((const void *)pair_gram_kernel<PM>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
-        attr_bytes = lds;
+        allowed = lds;
     }
     const u64 S = (u64)c->nq * c->N, client_stride = (u64)len * 2 * S;
     const int P = n * (n - 1) / 2;
