@@ -6,6 +6,9 @@ three limbs and three windows of 32 coefficients (the range's start, middle
 and end):
   * the pair kernel (a2): the first, a middle and the last pair;
   * the plaintext-mask aggregate (a6): every packed ciphertext and component.
+Relinearization (a3) at the same ring degree and limb count is checked whole
+against the oracle (the hoisted rotate-and-sum at that shape is in
+test_gpu_parity.py).
 """
 import gc
 
@@ -90,3 +93,24 @@ def test_masked_sum_full_size_sampled(torch, oracle_mod, full):
     finally:
         del out, masks
         torch.cuda.empty_cache()
+
+
+def test_relin_full_shape(torch, L, oracle_mod):
+    """Relinearization (a3) at N = 2^16 with 24 + 4 limbs (dnum 6) in the
+    bench's key-switch configuration (batch of 32, 16 ciphertexts per lane of
+    the inner product, fused ModUp / ModDown passes), on two synthetic
+    degree-2 ciphertexts with uniform residues, against the oracle's
+    relinearization with the same relinearization key."""
+    O = oracle_mod
+    prm = (LOG_N, (50,) * NQ, (50,) * 4)
+    ctx = L.Context(*prm, device=0)
+    ctx.keygen(29)
+    ora = O.Oracle(*prm)
+    assert ora.primes == ctx.moduli
+    rlk = ora.relin_key(29, ora.secret(29))
+    ctx.set_tuning("ks_chunk", 32)
+    ctx.set_tuning("mac_cts", 16)
+    t3 = synth.uniform_residues(3131, ctx.q, (2, 3, ctx.N))
+    got = ctx.relin(torch.from_numpy(t3.view(np.int64)).cuda()).cpu().numpy().view(np.uint64)
+    for c in range(2):
+        assert np.array_equal(got[c], ora.relin(t3[c], rlk)), c
