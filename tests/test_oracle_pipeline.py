@@ -2,10 +2,14 @@
 decrypted pairwise distances against FP64 numpy distances of the same
 synthetic updates, and the KGC selection rules against FP64 selections.
 """
+import pathlib
+
 import numpy as np
 import pytest
 
 import synth
+
+GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 
 def run_pipeline(O, w, plan=None, want_triples=False):
@@ -93,12 +97,12 @@ def test_selection_rules_fp64(oracle_mod):
 
 
 def test_permutation_mask_example(oracle_mod):
-    """Five clients, top three are clients 1, 3, 5 (1-based): rows e_1, e_3, e_5, o, o."""
+    """The paper's worked mask example (tests/golden/permutation_mask_5clients.txt):
+    five clients, the top three are clients 1, 3, 5 (1-based)."""
     O = oracle_mod
-    P = O.permutation_mask(5, [0, 2, 4])
-    want = np.zeros((5, 5), dtype=np.int64)
-    want[0, 0] = want[1, 2] = want[2, 4] = 1
-    assert np.array_equal(P, want)
+    want = np.loadtxt(GOLDEN / "permutation_mask_5clients.txt", comments="#", dtype=np.int64)
+    assert want.shape == (5, 5)
+    assert np.array_equal(O.permutation_mask(5, [0, 2, 4]), want)
 
 
 def test_pair_triple_columns_pins(oracle_mod):

@@ -1,6 +1,8 @@
 """The KGC's selection (Algorithm 2) and mask plaintexts, product code
 against the oracle's independent implementation and against the paper's
 worked example; runs on the CPU."""
+import pathlib
+
 import numpy as np
 import pytest
 
@@ -42,9 +44,12 @@ def test_multikrum_stopping_rule():
 
 
 def test_paper_example_mask_rows():
-    """The 5-client example of Masked-based Encrypted Sorting: clients 1, 3, 5
-    (1-based) used, two zero rows; here as weights and constant plaintexts."""
-    chosen = [0, 2, 4]
+    """The 5-client example of Masked-based Encrypted Sorting
+    (tests/golden/permutation_mask_5clients.txt): clients 1, 3, 5 (1-based)
+    used, two zero rows; here as weights and constant plaintexts."""
+    P = np.loadtxt(pathlib.Path(__file__).parent / "golden" / "permutation_mask_5clients.txt", comments="#")
+    chosen = [int(j) for j in np.nonzero(P.any(axis=0))[0]]
+    assert chosen == [0, 2, 4]
     w = robust.weights("multikrum", chosen, 5)
     assert np.allclose(w, [1 / 3, 0, 1 / 3, 0, 1 / 3])
     m = robust.mask_plaintexts(w, 16, 2.0 ** 40)
