@@ -6,8 +6,9 @@ three limbs and three windows of 32 coefficients (the range's start, middle
 and end):
   * the pair kernel (a2): the first, a middle and the last pair;
   * the plaintext-mask aggregate (a6): every packed ciphertext and component.
-Relinearization (a3) at the same ring degree and limb count is checked whole
-against the oracle (the hoisted rotate-and-sum at that shape is in
+Relinearization (a3), encryption (a1), decryption (a7) and hoisted rotations
+(a4, the literal form) at the same ring degree and limb count are checked
+whole against the oracle (the hoisted rotate-and-sum at that shape is in
 test_gpu_parity.py).
 """
 import gc
@@ -114,3 +115,34 @@ def test_relin_full_shape(torch, L, oracle_mod):
     got = ctx.relin(torch.from_numpy(t3.view(np.int64)).cuda()).cpu().numpy().view(np.uint64)
     for c in range(2):
         assert np.array_equal(got[c], ora.relin(t3[c], rlk)), c
+
+
+def test_encrypt_decrypt_rotate_full_shape(torch, L, oracle_mod):
+    """Encryption (a1), decryption of 2- and 3-component ciphertexts (a7) and
+    hoisted rotations over several steps sharing one ModUp (a4, the literal
+    form) at N = 2^16 with 24 + 4 limbs, against the oracle with the same
+    keys and the same counter-based randomness."""
+    O = oracle_mod
+    prm = (LOG_N, (50,) * NQ, (50,) * 4)
+    steps = [1, 64, -5]
+    ctx = L.Context(*prm, device=0)
+    ctx.keygen(31)
+    ctx.keygen_rotation(31, steps)
+    ora = O.Oracle(*prm)
+    assert ora.primes == ctx.moduli
+    s = ora.secret(31)
+    pk = ora.pk(31, s)
+    rng = np.random.default_rng(12)
+    m = rng.integers(-(1 << 40), 1 << 40, size=(2, ctx.N), dtype=np.int64)
+    want = ora.encrypt(88, 500, m, pk)
+    got = ctx.encrypt(torch.from_numpy(m).cuda(), seed=88, first_object=500)
+    assert np.array_equal(got.cpu().numpy().view(np.uint64), want)
+    dec = ctx.decrypt(got).cpu().numpy().view(np.uint64)
+    for t in range(2):
+        assert np.array_equal(dec[t], ora.decrypt(want[t], s)), t
+    t3 = ora.mul(want[0], want[1])
+    d3 = ctx.decrypt(torch.from_numpy(t3[None].view(np.int64)).cuda(), ncomp=3).cpu().numpy().view(np.uint64)[0]
+    assert np.array_equal(d3, ora.decrypt(t3, s))
+    rks = [ora.rot_key(31, s, k) for k in steps]
+    rot = ctx.rotate_hoisted(got[:1].contiguous(), steps).cpu().numpy().view(np.uint64)
+    assert np.array_equal(rot[0], ora.rotate_hoisted(want[0], steps, rks))
