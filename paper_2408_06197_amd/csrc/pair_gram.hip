@@ -31,6 +31,11 @@
 // tiles per item kept across all chunks.  At the end the items are reduced mod
 // q into an LDS copy of G and the pair triples read off it.  The copy of chunk
 // k + 1 runs while chunk k is multiplied.
+//
+// Status: an option (tuning "pair_mfma").  The 13 accumulator tiles per item
+// limit a CU to a few coefficients in flight, so each client row is read 16 or
+// 32 bytes at a time; on MI355X at N = 2^16 with 20 clients this measured
+// slower than the per-pair FP64 kernel, which stays the default.
 #include "lc_internal.h"
 
 namespace lc {
@@ -46,7 +51,7 @@ constexpr int PG_MAXR = 48;   // rows 2n: at most 3 row blocks of 16
 template <int PM>
 struct PgShape {
     static constexpr int SEG = PM * 8;                 // bytes per (row, ciphertext) in the copy buffer
-    static constexpr int RS = PG_KC * SEG + 16;        // bytes per copy-buffer row (padded: no bank conflicts)
+    static constexpr int RS = PG_KC * SEG + 16;        // bytes per copy-buffer row (padded to spread rows over banks)
     static constexpr int SPL = 1024 / SEG;             // segments per wave copy (16 bytes per lane)
     static constexpr int LPS = SEG / 16;               // lanes per segment
     static constexpr int IPR = PG_KC / SPL;            // wave copies per row
