@@ -48,6 +48,10 @@ def full(torch, L):
     assert all(int(q) > 1 << 49 for q in ctx.q)  # 49-bit inputs are canonical for every limb
     gc.collect()
     torch.cuda.empty_cache()
+    need = N_CLIENTS * LEN * 2 * NQ * (8 << LOG_N) + (20 << 30)  # ciphertexts + outputs and workspace
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"the full-size workload needs {need / 2**30:.0f} GiB free on the device, {free / 2**30:.0f} GiB is")
     cts = synth.device_residues(torch, 4242, 49, (N_CLIENTS, LEN, 2, NQ, 1 << LOG_N))
     yield ctx, cts
     del cts
