@@ -92,3 +92,48 @@ def test_samplers_follow_stream(oracle_mod):
     for c in range(8):
         hi, lo = O.draw_word(seed, 2, obj, 2 * c), O.draw_word(seed, 2, obj, 2 * c + 1)
         assert int(u[c]) == ((hi << 64) | lo) % q
+
+
+def _cdt_exact_mpmath():
+    import mpmath
+    with mpmath.workdps(120):
+        sigma = mpmath.mpf(16) / 5  # 3.2 exactly
+        rho = [mpmath.exp(-mpmath.mpf(t * t) / (2 * sigma * sigma)) for t in range(-19, 20)]
+        total = mpmath.fsum(rho)
+        out, acc, margin = [], mpmath.mpf(0), mpmath.mpf(1)
+        for k in range(38):
+            acc += rho[k]
+            v = acc / total * mpmath.mpf(2) ** 64
+            f = mpmath.floor(v)
+            margin = min(margin, v - f, f + 1 - v)
+            out.append(int(f))
+        return out, margin
+
+
+def _cdt_exact_decimal():
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 90
+        two_sigma2 = 2 * (Decimal(16) / Decimal(5)) ** 2
+        rho = [(-Decimal(t * t) / two_sigma2).exp() for t in range(-19, 20)]
+        total = sum(rho, Decimal(0))
+        out, acc = [], Decimal(0)
+        for k in range(38):
+            acc += rho[k]
+            out.append(int((acc / total * Decimal(2) ** 64).to_integral_value(rounding="ROUND_FLOOR")))
+        return out
+
+
+def test_cdt_table_exact(oracle_mod):
+    """The 38 stored thresholds T[t] = floor(2^64 P(X <= t)) of the
+    sigma = 3.2 discrete Gaussian on [-19, 19] (the error distribution of
+    key generation and encryption, CKKS Scheme Description), recomputed in the
+    test at 120 digits with mpmath and at 90 digits with the standard
+    library's decimal, and equal to the oracle's table in every bit.  Every
+    value lies more than 2^-200 from an integer, so the floors are robust."""
+    T = [int(x) for x in oracle_mod.cdt_table()]
+    ref, margin = _cdt_exact_mpmath()
+    assert T == ref
+    assert T == _cdt_exact_decimal()
+    import mpmath
+    assert margin > mpmath.mpf(2) ** -200
