@@ -117,6 +117,23 @@ int lc_pk_export(const lc_ctx *ctx, uint64_t *pk_host);
  * which = 1 rotation key for `step`. */
 int lc_ksk_export(const lc_ctx *ctx, int which, int step, uint64_t *ksk_host);
 
+/* Imports a key made outside the library, for instance by an independent
+ * implementation from the same secret, so that every server operation can be
+ * checked without relying on lc_keygen (CKKS Scheme Description, key
+ * generation; Methods, Dynamic Hoisting for the digit form).  kind:
+ *   LC_KEY_PK        host_blob = pk [2][n_q][N];
+ *   LC_KEY_RELIN     host_blob = relinearization key [dnum][2][n_q + n_p][N];
+ *   LC_KEY_ROTATION  host_blob = key of slot rotation `step` (Galois element
+ *                    5^step mod 2N), same layout as the relinearization key.
+ * NTT domain, residues canonical (checked on the host: LC_EINVAL).  Any role;
+ * a key already present is replaced (the device is synchronized first).
+ * `step` is ignored unless kind is LC_KEY_ROTATION.  Synchronous; the caller
+ * keeps ownership of host_blob. */
+#define LC_KEY_PK 0
+#define LC_KEY_RELIN 1
+#define LC_KEY_ROTATION 2
+int lc_key_import(lc_ctx *ctx, int kind, int step, const uint64_t *host_blob);
+
 /* ---- encode / decode (host, FP64; Methods, Batch Encoding and Decoding) -- */
 
 /* m = round(scale * sigma^-1(pi^-1(z))), z real (z_im NULL) or complex with
@@ -234,6 +251,19 @@ int lc_pairwise_finish(lc_ctx *ctx, const uint64_t *triples_dev, int n, const in
 int lc_pairwise_sqdist(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const int *plan, int nblocks,
                        uint64_t *dist_dev, uint64_t *sumdis_dev, void *stream);
 
+/* SumDis with one relinearization and one rotate-and-sum per client instead
+ * of per pair (Algorithm 1, the SumDis line; Methods, Lazy Relinearization:
+ * all squared-difference triples are summed before the single
+ * relinearization): sumdis[i] = RotSum(Relin(sum_{j != i} sum_{k < len}
+ * (ct_i[k] - ct_j[k])^2)).  It decrypts to the same value as the SumDis of
+ * lc_pairwise_sqdist (within the key-switching noise) with n instead of
+ * n(n-1)/2 key-switching chains.  client_cts [n][len][2][n_q][N],
+ * sumdis [n][2][n_q][N] (must not overlap the input); 2 <= n <= 64; plan as
+ * for lc_rotate_sum.  Scratch: the stream's workspace ((P + n) triples plus
+ * the key-switch batch). */
+int lc_sumdis_lazy(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const int *plan, int nblocks,
+                   uint64_t *sumdis_dev, void *stream);
+
 /* ServerUpdate with an encrypted mask (Algorithm 1, ServerUpdate; Methods,
  * Masked-based Encrypted Sorting): out[k] = relin(sum_i ct_i[k] (x) M_i),
  * the client ciphertexts [n][len][2][n_q][N] times each client's mask
@@ -253,10 +283,52 @@ int lc_mask_aggregate(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int le
 int lc_ntt_fwd(lc_ctx *ctx, uint64_t *polys_dev, size_t count, int nlimb, int limb0, void *stream);
 int lc_ntt_inv(lc_ctx *ctx, uint64_t *polys_dev, size_t count, int nlimb, int limb0, void *stream);
 
+/* A group of limb-polynomials for the mixed-degree transforms: count
+ * polynomials of nlimb limbs of ring degree 2^log_n each, [count][nlimb][2^log_n]
+ * contiguous at data (device memory); limb l of each uses modulus limb0 + l
+ * of the extended basis. */
+typedef struct lc_poly_group {
+    uint64_t *data;
+    size_t count;
+    int log_n;
+    int nlimb;
+    int limb0;
+} lc_poly_group;
+/* In-place forward / inverse negacyclic NTTs of polynomials of mixed ring
+ * degree, all groups in one launch per pass (two passes per direction;
+ * Appendix, Descriptions of Hardware Acceleration: the batched NTT).  A
+ * degree-2^k polynomial is transformed with psi_k, the smallest primitive
+ * 2^(k+1)-th root of unity of its modulus, so its result equals lc_ntt_fwd /
+ * lc_ntt_inv of a context of degree 2^k with the same moduli.  Needs
+ * 12 <= log_n <= min(16, the context's log_n) (LC_EUNSUP) and 1 <= ngroups
+ * <= 16 (LC_EINVAL); every modulus of the context is = 1 mod 2N, hence also
+ * mod 2^(k+1).  The first call with a degree below the context's uploads that
+ * degree's twiddle tables (synchronous). */
+int lc_ntt_fwd_groups(lc_ctx *ctx, const lc_poly_group *groups, int ngroups, void *stream);
+int lc_ntt_inv_groups(lc_ctx *ctx, const lc_poly_group *groups, int ngroups, void *stream);
+
 /* ---- memory planning ------------------------------------------------------- */
 
 /* Workspace bytes that lc_pairwise_sqdist needs for n clients. */
 int lc_workspace_query(const lc_ctx *ctx, int n, int len, size_t *bytes);
+/* HBM footprint of one pairwise-distance round of n clients x len packed
+ * ciphertexts (Methods, Dynamic Hoisting, on the memory a batch needs), for
+ * admission control.  k_chunk = 0: the client ciphertexts are resident and
+ * the round runs lc_pairwise_sqdist; 0 < k_chunk < len: they arrive in chunks
+ * of k_chunk that lc_pair_triples_acc folds into a triple buffer, then
+ * lc_pairwise_finish.  *round_bytes (may be NULL): the buffers the caller
+ * holds for the round -- client ciphertexts (all, or one chunk), distance
+ * ciphertexts, the triple buffer when streamed, and with flags
+ * LC_FP_SUMDIS the SumDis ciphertexts, LC_FP_PLAINTEXTS one chunk of int64
+ * plaintexts to encrypt, LC_FP_DECRYPT the decrypted distances [P][n_q][N].
+ * *workspace_bytes (may be NULL): the library workspace those calls grow on
+ * the round's stream (kept by the stream afterwards).  LC_EINVAL for n < 2
+ * or len < 1. */
+#define LC_FP_SUMDIS 1
+#define LC_FP_PLAINTEXTS 2
+#define LC_FP_DECRYPT 4
+int lc_footprint(const lc_ctx *ctx, int n, int len, int k_chunk, int flags, size_t *round_bytes,
+                 size_t *workspace_bytes);
 /* Caps the workspace the library may hold (0 = no cap); calls that would
  * need more run in smaller batches, or fail with LC_ENOMEM. */
 int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);

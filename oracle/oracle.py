@@ -604,6 +604,30 @@ class Oracle:
             raise ValueError("pairwise failed")
         return {"dist": dist, "sumdis": sumdis, "triples": triples}
 
+    def pair_distance(self, cts, i, j, rlk, plan, rks):
+        """One pair's distance ciphertext (Algorithm 1, Server Executes): the
+        lazily accumulated triple of (i, j), one relinearization, then the
+        rotate-and-sum with `plan` -- what `pairwise` computes for that pair."""
+        return self.rotate_sum(self.relin(self.pair_triple(cts, i, j), rlk), plan, rks)
+
+    def sumdis_lazy(self, cts, rlk, plan, rks, clients=None):
+        """SumDis with one relinearization per client (Algorithm 1, the SumDis
+        line; Methods, Lazy Relinearization: triples are summed before the
+        single relinearization): for client i, the squared-difference triples
+        of every pair (i, j), j != i, summed over the packed ciphertexts and
+        over j, then relinearized once and rotate-summed with `plan`.
+        cts [n][len][2][nq][N] -> [len(clients)][2][nq][N]."""
+        n = cts.shape[0]
+        out = []
+        for i in (range(n) if clients is None else clients):
+            acc = None
+            for j in range(n):
+                if j != i:
+                    t = self.pair_triple(cts, min(i, j), max(i, j))
+                    acc = t if acc is None else self.add(acc, t)
+            out.append(self.rotate_sum(self.relin(acc, rlk), plan, rks))
+        return np.stack(out)
+
     def masked_sum(self, cts, masks_ntt):
         cts = _u(cts)
         n, ln = cts.shape[0], cts.shape[1]

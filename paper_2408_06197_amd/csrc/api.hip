@@ -375,6 +375,66 @@ int lc_ksk_export(const lc_ctx *x, int which, int step, uint64_t *out)
     return LC_OK;
 }
 
+static bool canonical_limbs(const Ctx *c, const u64 *h, u64 count, int nlimb)
+{
+    for (u64 o = 0; o < count; o++)
+        for (int l = 0; l < nlimb; l++) {
+            const u64 m = c->mod[l], *p = h + (o * nlimb + l) * c->N;
+            for (u64 j = 0; j < c->N; j++)
+                if (p[j] >= m) return false;
+        }
+    return true;
+}
+
+int lc_key_import(lc_ctx *x, int kind, int step, const uint64_t *blob)
+{
+    CHECK_CTX(x);
+    if (!blob) return fail(c, LC_EINVAL, "null key");
+    const u64 S = (u64)c->nq * c->N, NE = (u64)c->ne * c->N, K = (u64)c->dnum * 2 * NE;
+    if (kind == LC_KEY_PK) {
+        if (!canonical_limbs(c, blob, 2, c->nq)) return fail(c, LC_EINVAL, "key residues must be canonical");
+        if (!c->pk) {
+            c->pk = (u64 *)dev_alloc(c, 2 * S * 8);
+            c->pk_sh = (u64 *)dev_alloc(c, 2 * S * 8);
+            if (!c->pk || !c->pk_sh) return fail(c, LC_ENOMEM, "key allocation failed");
+            c->key_bytes += 4 * S * 8;
+        }
+        LC_HIP(c, hipDeviceSynchronize());
+        LC_HIP(c, hipMemcpy(c->pk, blob, 2 * S * 8, hipMemcpyHostToDevice));
+        return upload_shoup(c, c->pk, c->pk_sh, c->nq, 2);
+    }
+    if (kind != LC_KEY_RELIN && kind != LC_KEY_ROTATION) return fail(c, LC_EINVAL, "unknown key kind");
+    if (!canonical_limbs(c, blob, (u64)c->dnum * 2, c->ne)) return fail(c, LC_EINVAL, "key residues must be canonical");
+    u64 *dst;
+    if (kind == LC_KEY_RELIN) {
+        if (!c->rlk) {
+            c->rlk = (u64 *)dev_alloc(c, K * 8);
+            if (!c->rlk) return fail(c, LC_ENOMEM, "key allocation failed");
+            c->key_bytes += K * 8;
+        }
+        dst = c->rlk;
+    } else {
+        const u64 g = galois_of_step(c->log_n, step);
+        if (g == 1) return fail(c, LC_EINVAL, "step is a multiple of N/2: no rotation");
+        auto it = c->rot.find(g);
+        if (it == c->rot.end()) {
+            u32 *perm = get_perm(c, g);
+            u64 *k = (u64 *)dev_alloc(c, K * 8);
+            if (!perm || !k) return fail(c, LC_ENOMEM, "rotation key allocation failed");
+            c->key_bytes += K * 8;
+            c->rot[g] = RotKey{k, perm, g};
+            int rc = build_cycle_table(c, g);
+            if (rc) return rc;
+            it = c->rot.find(g);
+        }
+        dst = it->second.ksk;
+    }
+    // work queued on any stream may still read the key being replaced
+    LC_HIP(c, hipDeviceSynchronize());
+    LC_HIP(c, hipMemcpy(dst, blob, K * 8, hipMemcpyHostToDevice));
+    return LC_OK;
+}
+
 // ---- encode / decode ------------------------------------------------------------
 
 int lc_encode(const lc_ctx *x, const double *re, const double *im, size_t nslots, double scale, int64_t *m)
@@ -704,7 +764,7 @@ static int pairwise_finish(lc_ctx *x, Ctx *c, const u64 *d01_base, u64 d01_strid
     int rc;
     if ((rc = keyswitch_hoisted(c, d2, d2_stride, P, &g, 1, s))) return rc;
     if ((rc = lc_rotate_sum(x, dist, P, plan, nblocks, stream))) return rc;
-    if (sumdis) return launch_sumdis(c, dist, n, sumdis, s);
+    if (sumdis) return launch_sumdis(c, dist, 2 * S, n, 2, sumdis, s);
     return LC_OK;
 }
 
@@ -739,6 +799,80 @@ int lc_pairwise_sqdist(lc_ctx *x, const uint64_t *cts, int n, int len, const int
     return pairwise_finish(x, c, dist, 2 * S, d2, S, n, plan, nblocks, dist, sumdis, stream);
 }
 
+int lc_sumdis_lazy(lc_ctx *x, const uint64_t *cts, int n, int len, const int *plan, int nblocks, uint64_t *sumdis,
+                   void *stream)
+{
+    CHECK_CTX(x);
+    if (!cts || !sumdis) return fail(c, LC_EINVAL, "null buffer");
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    if (n < 2 || n > 64) return fail(c, LC_EINVAL, "pairwise kernels take 2..64 clients");
+    if (len < 1) return fail(c, LC_EINVAL, "need len >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
+    const u64 P = (u64)n * (n - 1) / 2;
+    if (overlap(cts, (u64)n * len * 2 * S * 8, sumdis, (u64)n * 2 * S * 8))
+        return fail(c, LC_EINVAL, "sumdis must not overlap the client ciphertexts");
+    // pair triples, then each client's sum of its n - 1 triples
+    u64 *trip = ws_get(c, WS_PIPE, (P + (u64)n) * 3 * S * 8, s);
+    if (!trip) return LC_ENOMEM;
+    u64 *sums = trip + P * 3 * S;
+    int rc;
+    if ((rc = launch_pair_triples(c, cts, n, len, trip, 3 * S, trip + 2 * S, 3 * S, 0, s))) return rc;
+    if ((rc = launch_sumdis(c, trip, 3 * S, n, 3, sums, s))) return rc;
+    KsGroup g{};
+    g.keys[0] = c->rlk;
+    g.n = 1;
+    g.base = sums;
+    g.base_stride = 3 * S;
+    g.out = sumdis;
+    g.out_stride = 2 * S;
+    if ((rc = keyswitch_hoisted(c, sums + 2 * S, 3 * S, (u64)n, &g, 1, s))) return rc;
+    return lc_rotate_sum(x, sumdis, (size_t)n, plan, nblocks, stream);
+}
+
+static int ntt_groups(lc_ctx *x, const lc_poly_group *groups, int ngroups, void *stream, bool inverse)
+{
+    CHECK_CTX(x);
+    if (ngroups < 1 || ngroups > MAX_MIXED || !groups) return fail(c, LC_EINVAL, "1..16 polynomial groups");
+    MixedArgs ma{};
+    for (int d = MIXED_LOG_MIN; d <= MIXED_LOG_MAX && d <= c->log_n; d++) {
+        DegreeTables t;
+        bool used = false;
+        for (int g = 0; g < ngroups; g++) used |= groups[g].log_n == d && groups[g].count > 0;
+        if (!used) continue;
+        int rc = degree_tables(c, d, &t);
+        if (rc) return rc;
+        ma.tw[d - MIXED_LOG_MIN] = inverse ? t.itwd : t.twd;
+        ma.ninv[d - MIXED_LOG_MIN] = t.ninv;
+    }
+    for (int g = 0; g < ngroups; g++) {
+        const lc_poly_group &G = groups[g];
+        if (G.log_n < MIXED_LOG_MIN || G.log_n > std::min(MIXED_LOG_MAX, c->log_n))
+            return fail(c, LC_EUNSUP, "group ring degrees must lie in 2^12 .. min(2^16, N)");
+        if (G.nlimb < 1 || G.limb0 < 0 || G.limb0 + G.nlimb > c->ne) return fail(c, LC_EINVAL, "limb range outside the basis");
+        if (G.count && !G.data) return fail(c, LC_EINVAL, "null buffer");
+        if (!G.count) continue;
+        MixedGroup &M = ma.g[ma.ng++];
+        M.base = G.data;
+        M.npoly = (u64)G.count * G.nlimb;
+        M.nlimb = G.nlimb;
+        M.limb0 = G.limb0;
+        M.log_n = G.log_n;
+    }
+    if (!ma.ng) return LC_OK;
+    return launch_ntt_mixed(c, ma, inverse, (hipStream_t)stream);
+}
+
+int lc_ntt_fwd_groups(lc_ctx *x, const lc_poly_group *groups, int ngroups, void *stream)
+{
+    return ntt_groups(x, groups, ngroups, stream, false);
+}
+
+int lc_ntt_inv_groups(lc_ctx *x, const lc_poly_group *groups, int ngroups, void *stream)
+{
+    return ntt_groups(x, groups, ngroups, stream, true);
+}
+
 int lc_ntt_fwd(lc_ctx *x, uint64_t *polys, size_t count, int nlimb, int limb0, void *stream)
 {
     CHECK_CTX(x);
@@ -770,6 +904,30 @@ int lc_workspace_query(const lc_ctx *x, int n, int len, size_t *bytes)
     const u64 S = (u64)c->nq * c->N, P = (u64)n * (n - 1) / 2;
     u64 chunk = std::min<u64>(P, (u64)c->tune.ks_chunk);
     *bytes = (P * S + chunk * ks_words_per_ct(c) + chunk * 2 * S) * 8;
+    return LC_OK;
+}
+
+int lc_footprint(const lc_ctx *x, int n, int len, int k_chunk, int flags, size_t *round_bytes, size_t *workspace_bytes)
+{
+    if (!x || n < 2 || len < 1 || k_chunk < 0) return LC_EINVAL;
+    const Ctx *c = &x->c;
+    const u64 S = (u64)c->nq * c->N, P = (u64)n * (n - 1) / 2;
+    const u64 k = k_chunk ? std::min<u64>((u64)k_chunk, (u64)len) : (u64)len;
+    // caller-held buffers of the round
+    u64 words = (u64)n * k * 2 * S + P * 2 * S;      // client ciphertexts (a chunk of k), distances
+    if (k < (u64)len) words += P * 3 * S;             // streamed: the lazy triples accumulate in a buffer
+    if (flags & LC_FP_SUMDIS) words += (u64)n * 2 * S;
+    if (flags & LC_FP_PLAINTEXTS) words += (u64)n * k * c->N;
+    if (flags & LC_FP_DECRYPT) words += P * S;
+    // library workspace on the round's stream: the pipeline's d2 (resident
+    // form), the key-switch batch, the rotate-and-sum ping-pong buffer and
+    // (streamed form) the encryption staging of one chunk
+    const u64 kc = std::min<u64>(P, (u64)c->tune.ks_chunk);
+    u64 ws = kc * ks_words_per_ct(c) + kc * 2 * S;
+    if (k < (u64)len) ws += std::min<u64>((u64)n * k, std::max<u64>(1, (1ull << 31) / (3 * S * 8))) * 3 * S;
+    else ws += P * S;
+    if (round_bytes) *round_bytes = words * 8;
+    if (workspace_bytes) *workspace_bytes = ws * 8;
     return LC_OK;
 }
 

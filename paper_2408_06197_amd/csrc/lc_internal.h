@@ -64,6 +64,13 @@ struct RotKey {
     u64 galois = 0;
 };
 
+// Twiddles (forward and inverse, as doubles, [ne][N]) and N^-1 mod m of one
+// ring degree.
+struct DegreeTables {
+    const double *twd = nullptr, *itwd = nullptr;
+    const u64 *ninv = nullptr;
+};
+
 struct Ctx {
     int device = 0, role = 0;
     int log_n = 0;
@@ -124,6 +131,7 @@ struct Ctx {
         int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
+    std::map<int, DegreeTables> degree_tabs;  // by log_n, below the context's degree
 };
 
 // error helpers (set ctx->err and return the code)
@@ -205,6 +213,28 @@ struct PolyBatch {
     const u64 *in_base = nullptr;
     u64 in_gstride = 0;  // in polynomials
 };
+// Polynomials of mixed ring degree 2^MIXED_LOG_MIN .. 2^16 in one launch per
+// pass: group g is npoly limb-polynomials of degree 2^log_n contiguous at
+// base, polynomial p using modulus limb0 + p % nlimb; tw / ninv hold each
+// degree's twiddles (inverse ones for inverse transforms) and N^-1, by
+// log_n - MIXED_LOG_MIN.  block0 is filled in by the launcher.
+constexpr int MIXED_LOG_MIN = 12, MIXED_LOG_MAX = 16, MAX_MIXED = 16;
+struct MixedGroup {
+    u64 *base;
+    u64 npoly;
+    u64 block0;
+    int nlimb, limb0, log_n;
+};
+struct MixedArgs {
+    MixedGroup g[MAX_MIXED];
+    int ng;
+    const double *tw[MIXED_LOG_MAX - MIXED_LOG_MIN + 1];
+    const u64 *ninv[MIXED_LOG_MAX - MIXED_LOG_MIN + 1];
+};
+int launch_ntt_mixed(Ctx *c, const MixedArgs &ma, bool inverse, hipStream_t s);
+// Twiddle tables of ring degree 2^log_n for the mixed launches (below the
+// context's degree: built on first use, synchronous upload).
+int degree_tables(Ctx *c, int log_n, DegreeTables *out);
 int launch_ntt_fwd(Ctx *c, const PolyBatch &b, hipStream_t s);
 int launch_ntt_inv(Ctx *c, const PolyBatch &b, hipStream_t s);
 
@@ -222,7 +252,9 @@ int launch_pair_gram(Ctx *c, int pm, const u64 *cts, int n, int len, u64 *d01, u
                      u64 d2_stride, int accumulate, hipStream_t s);
 int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d01_stride, u64 *d2, u64 d2_stride,
                         int accumulate, hipStream_t s);
-int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s);
+// out[i] = sum over j != i of in[pair (i, j)], ncomp components per object,
+// in_stride words between pairs; out [n][ncomp][nq][N]
+int launch_sumdis(Ctx *c, const u64 *dist, u64 in_stride, int n, int ncomp, u64 *sumdis, hipStream_t s);
 int launch_copy(Ctx *c, const u64 *src, u64 *dst, u64 words, hipStream_t s);
 
 // keys / rng (rng.hip)

@@ -184,34 +184,26 @@ __device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 
 // MODE (forward only): 1 / 2 = first pass with the ModUp / ModDown base
 // conversion (PolyBatch::conv), 3 = last pass with the ModDown combine
 // (PolyBatch::comb_*).
-template <int LOG_S, bool INVERSE, bool BLOCKS, int MODE = 0>
-__global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
+// One workgroup's pass over one tile of polynomial `poly` (ring degree
+// N_, modulus index mi, double twiddles tw of that degree and modulus;
+// ntab[mi] is the inverse pass's final scale unless pb.iscale is set).  src
+// is what a first pass reads; pidx is the polynomial's index in pb (used by
+// the fused conversion and combine modes).
+template <int LOG_S, bool INVERSE, bool BLOCKS, int MODE>
+__device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBatch &pb, u64 pidx, u64 *poly,
+                                              const u64 *src, int mi, u32 tile, u32 N_, const double *tw,
+                                              const u64 *ntab, int s0, int cols, int final_, double *lds)
 {
     constexpr u32 S = 1u << LOG_S;
     constexpr int LB = LOG_S - 4;
     constexpr u32 TPC = S / 16;  // lanes per sub-transform
-    extern __shared__ double lds[];
-    u64 *poly;
-    int mi;
-    u64 pidx = blockIdx.x;
-    if ((MODE == 1 || MODE == 2) && (pb.count & 7) == 0) {
-        // workgroups are dealt to the 8 XCDs round-robin: remap so that the
-        // limbs of one group run on one XCD and share its L2 copy of the
-        // group's conversion inputs
-        const u64 j = blockIdx.x >> 3, nl = (u64)pb.nlimb;
-        pidx = ((j / nl) * 8 + (blockIdx.x & 7)) * nl + j % nl;
-    }
-    const u64 *src;  // what the first pass reads
-    if (!poly_of_block(dp, pb, pidx, poly, mi, &src)) return;
     const double q = dp.mc[mi].qd, qinv = dp.mc[mi].qinv;
     const bool first_ = !final_;
     if (!first_) src = poly;
-    const u32 tile = blockIdx.y;
-    const u32 stride = dp.N >> (s0 + LOG_S);
+    const u32 stride = N_ >> (s0 + LOG_S);
     const u32 nthreads = blockDim.x;
     const u32 tid = threadIdx.x;
     const u32 nel = S * (u32)cols;
-    const double *tw = (INVERSE ? dp.itwd : dp.twd) + (u64)mi * dp.N;
     // tile geometry
     u64 hi_col = 0, lo0 = 0;
     if (!BLOCKS) {
@@ -324,7 +316,7 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
         }
         __syncthreads();
     }
-    const double ni = (double)(pb.iscale ? pb.iscale[mi] : dp.ninv[mi]);
+    const double ni = (double)(pb.iscale ? pb.iscale[mi] : ntab[mi]);
     if (MODE == 3) {  // forward, last pass: the ModDown combine
         // out = (acc - v) P^-1 (+ add) with v this transform's output:
         // |acc - v| < 4 q, so the product and the sum stay exact
@@ -390,6 +382,27 @@ __global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch p
     }
 }
 
+template <int LOG_S, bool INVERSE, bool BLOCKS, int MODE = 0>
+__global__ void __launch_bounds__(256) ntt_fast_kernel(DevParams dp, PolyBatch pb, int s0, int cols, int final_)
+{
+    extern __shared__ double lds[];
+    u64 *poly;
+    int mi;
+    u64 pidx = blockIdx.x;
+    if ((MODE == 1 || MODE == 2) && (pb.count & 7) == 0) {
+        // workgroups are dealt to the 8 XCDs round-robin: remap so that the
+        // limbs of one group run on one XCD and share its L2 copy of the
+        // group's conversion inputs
+        const u64 j = blockIdx.x >> 3, nl = (u64)pb.nlimb;
+        pidx = ((j / nl) * 8 + (blockIdx.x & 7)) * nl + j % nl;
+    }
+    const u64 *src;  // what the first pass reads
+    if (!poly_of_block(dp, pb, pidx, poly, mi, &src)) return;
+    const double *tw = (INVERSE ? dp.itwd : dp.twd) + (u64)mi * dp.N;
+    ntt_fast_body<LOG_S, INVERSE, BLOCKS, MODE>(dp, pb, pidx, poly, src, mi, blockIdx.y, dp.N, tw, dp.ninv, s0,
+                                                cols, final_, lds);
+}
+
 struct FastPass {
     int s0, log_s, blocks, cols;
 };
@@ -416,6 +429,75 @@ static void launch_fast_one(int log_s, dim3 grid, dim3 block, size_t lds, hipStr
     case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     }
+}
+
+// ---- mixed ring degrees in one launch per pass ------------------------------
+//
+// For 2^12 <= N <= 2^16 both passes of the two-pass plan have 4096-element
+// tiles and 256-lane workgroups (columns: LOG_S = floor(log N / 2), 4096 /
+// 2^LOG_S sub-transforms per tile; blocks: LOG_S = ceil(log N / 2)), so one
+// launch can hold polynomials of several degrees: workgroup b finds its group
+// (uniform over the workgroup), its polynomial and tile, and runs the pass
+// body of that degree with that degree's twiddles.
+
+template <bool INVERSE, bool BLOCKS, int LOG_S>
+__device__ __forceinline__ void mixed_body(const DevParams &dp, const PolyBatch &pb, u64 *poly, int mi, u32 tile,
+                                           u32 N_, const double *tw, const u64 *ntab, int final_, double *lds)
+{
+    const int log_n = 31 - __clz((int)N_);
+    const int s0 = BLOCKS ? log_n - LOG_S : 0;
+    ntt_fast_body<LOG_S, INVERSE, BLOCKS, 0>(dp, pb, 0, poly, poly, mi, tile, N_, tw, ntab, s0, 4096 >> LOG_S,
+                                             final_, lds);
+}
+
+template <bool INVERSE, bool BLOCKS>
+__global__ void __launch_bounds__(256) ntt_mixed_kernel(DevParams dp, MixedArgs ma, int final_)
+{
+    extern __shared__ double lds[];
+    const u64 b = blockIdx.x;
+    int gi = 0;
+    while (gi + 1 < ma.ng && b >= ma.g[gi + 1].block0) gi++;
+    const MixedGroup &G = ma.g[gi];
+    const u32 N_ = 1u << G.log_n;
+    const u32 tiles = N_ / 4096u;
+    const u64 local = b - G.block0;
+    const u64 p = local / tiles;
+    const u32 tile = (u32)(local % tiles);
+    const int mi = G.limb0 + (int)(p % (u64)G.nlimb);
+    u64 *poly = G.base + p * N_;
+    const int di = G.log_n - MIXED_LOG_MIN;
+    const double *tw = ma.tw[di] + (u64)mi * N_;
+    const u64 *ntab = ma.ninv[di];
+    const PolyBatch pb{};
+    const int ls = BLOCKS ? G.log_n - G.log_n / 2 : G.log_n / 2;
+    if (ls == 6) mixed_body<INVERSE, BLOCKS, 6>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
+    else if (ls == 7) mixed_body<INVERSE, BLOCKS, 7>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
+    else mixed_body<INVERSE, BLOCKS, 8>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
+}
+
+int launch_ntt_mixed(Ctx *c, const MixedArgs &ma0, bool inverse, hipStream_t s)
+{
+    MixedArgs ma = ma0;
+    u64 blocks = 0;
+    for (int g = 0; g < ma.ng; g++) {
+        ma.g[g].block0 = blocks;
+        blocks += ma.g[g].npoly * ((1ull << ma.g[g].log_n) / 4096);
+    }
+    if (blocks == 0) return LC_OK;
+    if (blocks > 0x7fffffffull) return fail(c, LC_EINVAL, "too many polynomials in one NTT launch");
+    const size_t lds = (size_t)4096 * 17 / 16 * sizeof(double);
+    const dim3 grid((u32)blocks), block(256);
+    if (!inverse) {
+        hipLaunchKernelGGL((ntt_mixed_kernel<false, false>), grid, block, lds, s, c->dp, ma, 0);
+        LC_HIP(c, hipGetLastError());
+        hipLaunchKernelGGL((ntt_mixed_kernel<false, true>), grid, block, lds, s, c->dp, ma, 1);
+    } else {
+        hipLaunchKernelGGL((ntt_mixed_kernel<true, true>), grid, block, lds, s, c->dp, ma, 0);
+        LC_HIP(c, hipGetLastError());
+        hipLaunchKernelGGL((ntt_mixed_kernel<true, false>), grid, block, lds, s, c->dp, ma, 1);
+    }
+    LC_HIP(c, hipGetLastError());
+    return LC_OK;
 }
 
 // Pass plan of the generic kernel: one pass up to N = 4096, two passes above.

@@ -554,31 +554,32 @@ int launch_pair_triples(Ctx *c, const u64 *cts, int n, int len, u64 *d01, u64 d0
 }
 
 // ---- SumDis[i] = sum_{j != i} Dis[i][j] -------------------------------------
+// (also the per-client sums of pair triples: ncomp 3, in_stride 3 n_q N)
 
 __global__ void __launch_bounds__(EW_THREADS)
-sumdis_kernel(DevParams dp, const u64 *dist, int n, u64 *sumdis, u64 total)
+sumdis_kernel(DevParams dp, const u64 *dist, u64 in_stride, int n, int ncomp, u64 *sumdis, u64 total)
 {
-    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over n * 2 * nq * N
+    u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over n * ncomp * nq * N
     if (e >= total) return;
-    u64 S2 = 2 * ((u64)dp.nq << dp.log_n);
-    int i = (int)(e / S2);
-    u64 r = e % S2;
+    u64 SC = (u64)ncomp * ((u64)dp.nq << dp.log_n);
+    int i = (int)(e / SC);
+    u64 r = e % SC;
     int l = (int)((r >> dp.log_n) % (u64)dp.nq);
     u64 q = dp.mc[l].m, acc = 0;
     for (int j = 0; j < n; j++) {
         if (j == i) continue;
         int a = i < j ? i : j, b = i < j ? j : i;
         int p = pair_index(n, a, b);
-        acc = add_mod(acc, dist[(u64)p * S2 + r], q);
+        acc = add_mod(acc, dist[(u64)p * in_stride + r], q);
     }
     sumdis[e] = acc;
 }
 
-int launch_sumdis(Ctx *c, const u64 *dist, int n, u64 *sumdis, hipStream_t s)
+int launch_sumdis(Ctx *c, const u64 *dist, u64 in_stride, int n, int ncomp, u64 *sumdis, hipStream_t s)
 {
-    u64 total = (u64)n * 2 * c->nq * c->N;
-    hipLaunchKernelGGL(sumdis_kernel, grid_for(total, EW_THREADS), dim3(EW_THREADS), 0, s, c->dp, dist, n, sumdis,
-                       total);
+    u64 total = (u64)n * ncomp * c->nq * c->N;
+    hipLaunchKernelGGL(sumdis_kernel, grid_for(total, EW_THREADS), dim3(EW_THREADS), 0, s, c->dp, dist, in_stride, n,
+                       ncomp, sumdis, total);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
 }

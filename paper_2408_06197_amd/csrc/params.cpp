@@ -129,6 +129,48 @@ static const T *upload(Ctx *c, const std::vector<T> &h)
     return d;
 }
 
+int degree_tables(Ctx *c, int log_n, DegreeTables *out)
+{
+    if (log_n == c->log_n) {
+        *out = DegreeTables{c->dp.twd, c->dp.itwd, c->dp.ninv};
+        return LC_OK;
+    }
+    if (log_n < 1 || log_n > c->log_n) return fail(c, LC_EINVAL, "ring degree above the context's");
+    auto it = c->degree_tabs.find(log_n);
+    if (it != c->degree_tabs.end()) {
+        *out = it->second;
+        return LC_OK;
+    }
+    // the same construction as the context's own tables, with the smallest
+    // primitive 2^(log_n + 1)-th root of each modulus
+    const int ne = c->ne;
+    const u64 N = 1ull << log_n;
+    std::vector<double> twd(ne * N), itwd(ne * N);
+    std::vector<u64> ninv(ne);
+    for (int l = 0; l < ne; l++) {
+        const u64 m = c->mod[l], psi = smallest_psi(m, log_n);
+        if (!psi) return fail(c, LC_EINVAL, "a modulus has no root of unity of that order");
+        const u64 ipsi = invm(psi, m);
+        std::vector<u64> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (u64 k = 1; k < N; k++) {
+            pw[k] = mulm(pw[k - 1], psi, m);
+            ipw[k] = mulm(ipw[k - 1], ipsi, m);
+        }
+        for (u64 k = 0; k < N; k++) {
+            const u64 r = bit_reverse(k, log_n);
+            twd[l * N + k] = (double)pw[r];
+            itwd[l * N + k] = (double)ipw[r];
+        }
+        ninv[l] = invm(N % m, m);
+    }
+    DegreeTables t{upload(c, twd), upload(c, itwd), upload(c, ninv)};
+    if (!t.twd || !t.itwd || !t.ninv) return fail(c, LC_ENOMEM, "could not upload twiddle tables");
+    c->degree_tabs[log_n] = t;
+    *out = t;
+    return LC_OK;
+}
+
 int build_params(Ctx *c, const lc_params *prm)
 {
     if (!prm) return fail(c, LC_EINVAL, "params is NULL");

@@ -36,6 +36,14 @@ class LcParams(_c.Structure):
     _fields_ = [("log_n", INT), ("n_q", INT), ("n_p", INT), ("q_bits", PINT), ("p_bits", PINT), ("log_m", INT)]
 
 
+class LcPolyGroup(_c.Structure):
+    _fields_ = [("data", VP), ("count", SZ), ("log_n", INT), ("nlimb", INT), ("limb0", INT)]
+
+
+KEY_PK, KEY_RELIN, KEY_ROTATION = 0, 1, 2
+FP_SUMDIS, FP_PLAINTEXTS, FP_DECRYPT = 1, 2, 4
+
+
 _SIGS = {
     "lc_ctx_create": [_c.POINTER(LcParams), INT, INT, _c.POINTER(VP)],
     "lc_ctx_destroy": [VP],
@@ -50,6 +58,7 @@ _SIGS = {
     "lc_secret_export": [VP, PI64],
     "lc_pk_export": [VP, PU64],
     "lc_ksk_export": [VP, INT, INT, PU64],
+    "lc_key_import": [VP, INT, INT, PU64],
     "lc_encode": [VP, PD, PD, SZ, _c.c_double, PI64],
     "lc_encode_device": [VP, VP, SZ, SZ, SZ, _c.c_double, VP, VP],
     "lc_decode": [VP, PU64, _c.c_double, PD, PD],
@@ -75,6 +84,10 @@ _SIGS = {
     "lc_pair_triples_acc": [VP, VP, INT, INT, VP, VP],
     "lc_pairwise_finish": [VP, VP, INT, PINT, INT, VP, VP, VP],
     "lc_pairwise_sqdist": [VP, VP, INT, INT, PINT, INT, VP, VP, VP],
+    "lc_sumdis_lazy": [VP, VP, INT, INT, PINT, INT, VP, VP],
+    "lc_ntt_fwd_groups": [VP, VP, INT, VP],
+    "lc_ntt_inv_groups": [VP, VP, INT, VP],
+    "lc_footprint": [VP, INT, INT, INT, INT, _c.POINTER(SZ), _c.POINTER(SZ)],
     "lc_ntt_fwd": [VP, VP, SZ, INT, INT, VP],
     "lc_ntt_inv": [VP, VP, SZ, INT, INT, VP],
     "lc_workspace_query": [VP, INT, INT, _c.POINTER(SZ)],
@@ -212,6 +225,15 @@ class Context:
             steps += [t << j0 for t in range(1, 1 << kb)]
             j0 += kb
         return steps
+
+    def key_import(self, kind, blob, step=0):
+        """Install a host key (numpy uint64: pk [2][nq][N] or a key-switching
+        key [dnum][2][ne][N]) made outside the library."""
+        b = np.ascontiguousarray(blob, dtype=np.uint64)
+        want = (2, self.nq, self.N) if kind == KEY_PK else (self.dnum, 2, self.ne, self.N)
+        if b.shape != want:
+            raise ValueError(f"key shape {b.shape}, expected {want}")
+        self._check(lib().lc_key_import(self._h, kind, step, b.ctypes.data_as(PU64)))
 
     # ---- host encode / decode ----
     def encode(self, z, scale):
@@ -395,6 +417,38 @@ class Context:
         self._check(lib().lc_pairwise_sqdist(self._h, _ptr(cts), n, ln, pa, nb, _ptr(out),
                                              _ptr(sumdis_out) if sumdis else None, _stream(stream)))
         return (out, sumdis_out) if sumdis else out
+
+    def sumdis_lazy(self, cts, plan=None, out=None, stream=None):
+        """Per-client SumDis with one relinearization and rotate-and-sum per
+        client: [n][2][n_q][N]."""
+        n, ln = cts.shape[0], cts.shape[1]
+        out = self.empty(n, 2, self.nq, self.N) if out is None else out
+        pa, nb = (None, 0) if plan is None else _ints(plan)
+        self._check(lib().lc_sumdis_lazy(self._h, _ptr(cts), n, ln, pa, nb, _ptr(out), _stream(stream)))
+        return out
+
+    def _groups(self, groups):
+        arr = (LcPolyGroup * max(1, len(groups)))()
+        for k, (t, log_n, nlimb, limb0) in enumerate(groups):
+            count = t.numel() // (nlimb << log_n)
+            arr[k] = LcPolyGroup(_ptr(t), count, log_n, nlimb, limb0)
+        return arr, len(groups)
+
+    def ntt_fwd_groups(self, groups, stream=None):
+        """groups: [(tensor [count][nlimb][2^log_n], log_n, nlimb, limb0)],
+        transformed in place, one launch per pass for all of them."""
+        arr, n = self._groups(groups)
+        self._check(lib().lc_ntt_fwd_groups(self._h, arr, n, _stream(stream)))
+
+    def ntt_inv_groups(self, groups, stream=None):
+        arr, n = self._groups(groups)
+        self._check(lib().lc_ntt_inv_groups(self._h, arr, n, _stream(stream)))
+
+    def footprint(self, n, len_, k_chunk=0, flags=0):
+        """(round bytes, workspace bytes) of a pairwise-distance round."""
+        rb, wb = SZ(), SZ()
+        self._check(lib().lc_footprint(self._h, n, len_, k_chunk, flags, _c.byref(rb), _c.byref(wb)))
+        return rb.value, wb.value
 
     def ntt_fwd(self, polys, nlimb, limb0=0, stream=None):
         count = polys.numel() // (nlimb * self.N)

@@ -3,8 +3,9 @@
     python -m paper_2408_06197_amd.profile_cases pair       # one pair-triple launch
     python -m paper_2408_06197_amd.profile_cases keyswitch  # one rotate-and-sum of 16 ciphertexts
     python -m paper_2408_06197_amd.profile_cases keyswitch fuse_modup=0   # with lc_set_tuning overrides
+    python -m paper_2408_06197_amd.profile_cases ntt        # forward + inverse NTT of 64 ciphertexts' limbs
 
-Both run at N = 2^16 with 24 + 4 limbs of 50 bits on random residues, then
+All run at N = 2^16 with 24 + 4 limbs of 50 bits on random residues, then
 copy 4 GiB with a plain device copy so that each counter can be scaled by
 what it reads for a copy of known size.  Counter passes each need a run of
 their own (rocprofv3 does not split counters over passes).
@@ -63,11 +64,32 @@ def keyswitch(tune, count=16, plan=(3, 3, 3, 3, 3)):
     _calibration_copy()
 
 
+def ntt(tune, count=64, reps=3):
+    """Forward then inverse NTT of count x 24 limb-polynomials (residues
+    uniform in each limb's range), `reps` times: the transform the
+    benchmark's NTT roofline entry times."""
+    ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
+    for k, v in tune.items():
+        ctx.set_tuning(k, v)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    x = torch.empty((count, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    for l in range(NQ):
+        x[:, l].random_(0, int(ctx.q[l]), generator=gen)
+    for _ in range(reps):
+        ctx.ntt_fwd(x, nlimb=NQ)
+        ctx.ntt_inv(x, nlimb=NQ)
+    torch.cuda.synchronize()
+    del x
+    _calibration_copy()
+
+
 if __name__ == "__main__":
     case = sys.argv[1] if len(sys.argv) > 1 else "pair"
-    if case not in ("pair", "keyswitch"):
-        sys.exit("cases: pair, keyswitch")
+    cases = {"pair": pair, "keyswitch": keyswitch, "ntt": ntt}
+    if case not in cases:
+        sys.exit("cases: " + ", ".join(cases))
     tune = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in sys.argv[2:])
     torch.cuda.set_device(0)
-    {"pair": pair, "keyswitch": keyswitch}[case](tune)
+    cases[case](tune)
     print(f"profile case {case} done", flush=True)

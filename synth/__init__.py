@@ -131,3 +131,17 @@ def device_residues(torch, rng_seed: int, bits: int, shape):
     t = torch.empty(tuple(shape), dtype=torch.int64, device="cuda")
     t.random_(0, 1 << bits, generator=g)
     return t
+
+
+def device_residues_mod(torch, rng_seed: int, moduli, shape):
+    """Uniform residues in [0, q_l) for each limb l, generated on the GPU from
+    a seeded torch generator (int64 storage): shape [..., nlimb, N] with the
+    limb axis second to last and len(moduli) == nlimb, so full-size inputs
+    span each limb's whole range and never cross the host."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(rng_seed)
+    t = torch.empty(tuple(shape), dtype=torch.int64, device="cuda")
+    assert t.shape[-2] == len(moduli)
+    for l, q in enumerate(moduli):
+        t[..., l, :].random_(0, int(q), generator=g)
+    return t

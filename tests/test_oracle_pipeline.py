@@ -142,3 +142,25 @@ def test_masked_sum_columns_pins(oracle_mod):
     hot = np.zeros((n, 32), dtype=np.uint64)
     hot[3] = 1
     assert np.array_equal(O.masked_sum_columns(cts[:, :, :, 0, :], hot, ora.q[0]), cts[3, :, :, 0, :])
+
+
+def test_sumdis_lazy_pins(oracle_mod):
+    """The per-client SumDis (one relinearization per client, Algorithm 1
+    SumDis line with Methods, Lazy Relinearization) decrypts to the FP64
+    sum of each client's squared distances, and with two clients it reduces
+    exactly to the one pair's distance ciphertext (the triple sum of either
+    client is the pair's triple)."""
+    O = oracle_mod
+    w = TINY2
+    ora, s, upd, cts, res, scale = run_pipeline(O, w)
+    seed = w.crypto_seed
+    rlk = ora.relin_key(seed, s)
+    plan = list(w.rot_plan)
+    rks = [ora.rot_key(seed, s, k) for k in ora.rotsum_steps(plan)]
+    got = ora.sumdis_lazy(cts, rlk, plan, rks)
+    D = O.distance_matrix(fp64_dists(upd), w.n_clients)
+    for i in range(w.n_clients):
+        v = ora.read_distance(ora.decrypt(got[i], s), scale * scale)
+        assert np.isclose(v, D[i].sum(), rtol=1e-3), (i, v, D[i].sum())
+    two = ora.sumdis_lazy(cts[:2], rlk, plan, rks)
+    assert np.array_equal(two[0], res["dist"][0]) and np.array_equal(two[1], res["dist"][0])
