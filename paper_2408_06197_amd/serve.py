@@ -51,6 +51,16 @@ class ChainInfo:
     nq: int
     np_: int
     scale_log2: int
+    # context whose lc_footprint sizes the rounds (the server context, so
+    # that its key-switch batch is the one counted); a host-only context of
+    # the same shape is made on first use when none is given
+    ctx: object = None
+
+    def sizing_ctx(self):
+        if self.ctx is None:
+            from . import lancelot as L
+            self.ctx = L.Context(self.log_n, (50,) * self.nq, (50,) * self.np_, device=-1)
+        return self.ctx
 
     @property
     def N(self):
@@ -68,13 +78,23 @@ class ChainInfo:
 
 
 def round_footprint(ch: ChainInfo, n: int, dim: int, k_chunk: int) -> int:
-    """Device bytes a round holds while admitted: one k-chunk of client
-    ciphertexts and their plaintexts, the P lazy triples, the P distance
-    ciphertexts and their decryptions."""
-    P = n * (n - 1) // 2
-    S = ch.nq * ch.N * 8
-    k = min(k_chunk, ch.n_ct(dim))
-    return n * k * (2 * S + ch.N * 8) + P * (3 * S + 2 * S + S)
+    """Device bytes a round holds while admitted (lc_footprint): its client
+    ciphertexts (all of them when they fit one k-chunk, else one chunk and
+    the P lazy triples), their plaintexts, the P distance ciphertexts and
+    their decryptions."""
+    from . import lancelot as L
+    rb, _ = ch.sizing_ctx().footprint(n, ch.n_ct(dim), k_chunk, L.FP_PLAINTEXTS | L.FP_DECRYPT)
+    return rb
+
+
+def stream_workspace(ch: ChainInfo, n_max: int, k_chunk: int) -> int:
+    """Library workspace one stream can grow for rounds of up to n_max clients
+    of a chain, resident (len <= k_chunk) or streamed (kept by the stream
+    between rounds)."""
+    from . import lancelot as L
+    ctx = ch.sizing_ctx()
+    return max(ctx.footprint(n_max, ln, k_chunk, L.FP_PLAINTEXTS | L.FP_DECRYPT)[1]
+               for ln in (k_chunk, k_chunk + 1))
 
 
 def make_stream(n_rounds: int, rate: float, chains: List[str], seed: int = 3000,
@@ -175,10 +195,28 @@ class Scheduler:
 
 
 def latency_stats(records: Dict[int, dict]) -> dict:
-    lat = np.array([r["latency"] for r in records.values()])
-    span = max(r["done"] for r in records.values()) - min(r["arrival"] for r in records.values())
+    """p50 / p99 / mean latency (arrival to completion), its split into
+    queueing (arrival to admission) and service (admission to completion),
+    rounds/s and client-pair distances/s over the span of the records."""
+    recs = list(records.values())
+    lat = np.array([r["latency"] for r in recs])
+    queue = np.array([r["admit"] - r["arrival"] for r in recs])
+    service = np.array([r["done"] - r["admit"] for r in recs])
+    span = max(r["done"] for r in recs) - min(r["arrival"] for r in recs)
+    pairs = sum(r["n"] * (r["n"] - 1) // 2 for r in recs)
     return {"rounds": len(lat), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "rounds_per_s": len(lat) / span if span > 0 else math.inf}
+            "mean_s": float(lat.mean()), "mean_queue_s": float(queue.mean()), "mean_service_s": float(service.mean()),
+            "rounds_per_s": len(lat) / span if span > 0 else math.inf,
+            "distances_per_s": pairs / span if span > 0 else math.inf}
+
+
+def latency_by_class(records: Dict[int, dict]) -> dict:
+    """latency_stats per (chain, clients, model dimension) class: the tail of
+    a mixed stream is set by its largest rounds' service time."""
+    classes: Dict[str, dict] = {}
+    for rid, r in records.items():
+        classes.setdefault("%s/n%d/dim%d" % (r["chain"], r["n"], r["dim"]), {})[rid] = r
+    return {k: latency_stats(v) for k, v in sorted(classes.items())}
 
 
 # --------------------------------------------------------------------------
@@ -319,16 +357,28 @@ class GpuExecutor:
         pool = self.pools[spec.chain]
         n, P, ln = spec.n, spec.n * (spec.n - 1) // 2, ch.n_ct(spec.dim)
         with torch.cuda.stream(stream):
-            trip = torch.zeros((P, 3, ch.nq, ch.N), dtype=torch.int64, device="cuda")
-            for k0 in range(0, ln, self.k_chunk):
-                k = min(self.k_chunk, ln - k0)
-                m = self._plaintexts(spec, pool, ch, k0, k)
-                # PRNG objects n k0 .. n (k0 + k) - 1: distinct for every (chunk, client, k)
-                cts = srv.encrypt(m.view(n * k, ch.N), seed=spec.seed, first_object=n * k0, stream=stream)
-                srv.pair_triples_acc(cts.view(n, k, 2, ch.nq, ch.N), trip, stream=stream)
-                del m, cts
-            dist = srv.pairwise_finish(trip, n, plan=self.plans[spec.chain], stream=stream)
-            del trip
+            if ln <= self.k_chunk:
+                # resident: every packed ciphertext of the round on the device,
+                # then the batched pipeline in one call
+                m = self._plaintexts(spec, pool, ch, 0, ln)
+                cts = srv.encrypt(m.view(n * ln, ch.N), seed=spec.seed, first_object=0, stream=stream)
+                del m
+                dist = srv.pairwise_sqdist(cts.view(n, ln, 2, ch.nq, ch.N), plan=self.plans[spec.chain],
+                                           stream=stream)
+                del cts
+            else:
+                # streamed in chunks of k_chunk packed ciphertexts folded into
+                # the lazy triples (the same residues: modular sums are exact)
+                trip = torch.zeros((P, 3, ch.nq, ch.N), dtype=torch.int64, device="cuda")
+                for k0 in range(0, ln, self.k_chunk):
+                    k = min(self.k_chunk, ln - k0)
+                    m = self._plaintexts(spec, pool, ch, k0, k)
+                    # PRNG objects n k0 .. n (k0 + k) - 1: distinct for every (chunk, client, k)
+                    cts = srv.encrypt(m.view(n * k, ch.N), seed=spec.seed, first_object=n * k0, stream=stream)
+                    srv.pair_triples_acc(cts.view(n, k, 2, ch.nq, ch.N), trip, stream=stream)
+                    del m, cts
+                dist = srv.pairwise_finish(trip, n, plan=self.plans[spec.chain], stream=stream)
+                del trip
             dec = kgc.decrypt(dist, stream=stream)
             coeff0 = dec[:, :, 0].contiguous()
             ev = torch.cuda.Event()

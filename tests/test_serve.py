@@ -51,6 +51,17 @@ def test_footprint_formula():
     assert fp == 20 * 64 * (2 * S + 65536 * 8) + 190 * 6 * S
 
 
+def test_footprint_resident_round():
+    """A round whose packed ciphertexts fit one k-chunk is resident: all its
+    ciphertexts, no triple buffer (lc_pairwise_sqdist keeps d2 in its
+    workspace)."""
+    ch = CH["b"]
+    fp = serve.round_footprint(ch, 5, 100_000, 64)  # 4 packed ciphertexts per client
+    S = 24 * 65536 * 8
+    assert fp == 5 * 4 * (2 * S + 65536 * 8) + 10 * 3 * S
+    assert serve.stream_workspace(ch, 40, 64) > 0
+
+
 def test_admission_respects_slots_and_budget():
     clock = FakeClock()
     specs = serve.make_stream(60, rate=50.0, chains=["a", "b"], seed=5, dims=(100_000, 1_000_000))
@@ -170,3 +181,43 @@ def test_alone_equals_mix_and_decrypts():
         ref = serve.reference_distances(sp, pools[sp.chain], chains[sp.chain].n_ct(sp.dim))
         got = r["result"]["distances"]
         assert np.allclose(got, ref, rtol=1e-3), (rid, got, ref)
+
+
+@pytest.mark.gpu
+def test_alone_equals_mix_n16384_chain():
+    """The N = 2^14, 8 x 50-bit limb chain of the serving workload (2 special
+    primes, scale 2^40): rounds resident (at most 4 packed ciphertexts) and
+    streamed in chunks of 4, alone and in a mix of four streams, give the
+    same distance ciphertexts, which decrypt to the FP64 distances within
+    1e-4 relative."""
+    import torch
+    from paper_2408_06197_amd import lancelot as L
+
+    ch = serve.ChainInfo("n16384_l8", 14, 8, 2, 40)
+    kgc = L.Context(14, (50,) * 8, (50,) * 2, device=0, role=L.ROLE_KGC)
+    srv = L.Context(14, (50,) * 8, (50,) * 2, device=0, role=L.ROLE_SERVER)
+    plan = [3, 3, 3, 3, 1]
+    kgc.keygen(17)
+    kgc.keygen_rotation(17, kgc.rotsum_steps(plan))
+    kgc.keys_share(srv)
+    ch.ctx = srv
+    chains, contexts, plans = {"c": ch}, {"c": (kgc, srv)}, {"c": plan}
+    pools = {"c": serve.PlaintextPool(torch, srv, size=12, std=0.01, seed=13, scale=2.0 ** 40)}
+    specs = serve.make_stream(6, rate=0.0, chains=["c"], seed=21, clients=(3, 5), dims=(20_000, 100_000))
+    assert {ch.n_ct(s.dim) for s in specs} == {3, 13}
+
+    def run(sp, slots):
+        ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=4, streams=slots,
+                               keep_ciphertexts=True)
+        return serve.Scheduler(chains, 1 << 34, slots=slots, k_chunk=4).run(sp, ex)
+
+    alone = {}
+    for sp in specs:
+        alone.update(run([sp], 1))
+    mixed = run(specs, 4)
+    for rid, r in mixed.items():
+        assert np.array_equal(alone[rid]["result"]["dist_ct"].cpu().numpy(), r["result"]["dist_ct"].cpu().numpy())
+        sp = specs[rid]
+        ref = serve.reference_distances(sp, pools["c"], ch.n_ct(sp.dim))
+        got = r["result"]["distances"]
+        assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-4, (rid, got, ref)
