@@ -209,6 +209,19 @@ int lc_ct_square(lc_ctx *ctx, const uint64_t *a_dev, uint64_t *out3_dev, size_t 
  * Dynamic Hoisting).  in [count][3][n_q][N], out [count][2][n_q][N]; out must
  * not overlap in (LC_EINVAL). */
 int lc_relin(lc_ctx *ctx, const uint64_t *ct3_dev, uint64_t *ct2_dev, size_t count, void *stream);
+/* lc_relin for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and bits as lc_relin, but the key-switching scratch is a fixed
+ * device array of LC_NOALLOC_SCRATCH_MIB MiB that every GPU the library runs
+ * on holds from module load until the process ends; the call allocates
+ * nothing and runs in batches of as many ciphertexts as fit it.  LC_EINVAL
+ * when one ciphertext's scratch, (n_q + dnum (n_q + n_p) + 2 (n_q + n_p)
+ * + 2 n_q) N words (N = 2^16 with 24 + 4 limbs: 155 MB), exceeds the array.
+ * Every call on one GPU (any context, any stream) shares the array and keeps
+ * the last call's contents: calls that overlap on a GPU race, so the caller
+ * serializes them.  No word of it needs to start at zero. */
+#define LC_NOALLOC_SCRATCH_MIB 256
+int lc_relin_noalloc(lc_ctx *ctx, const uint64_t *ct3_dev, uint64_t *ct2_dev, size_t count, void *stream);
 /* Hoisted rotations (Methods, Dynamic Hoisting): one decomposition/ModUp of
  * c1 shared by all steps, then per step the automorphism on the raised
  * digits, the key inner product and ModDown.  outs [count][nsteps][2][n_q][N],

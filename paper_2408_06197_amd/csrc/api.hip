@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -105,6 +106,37 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb)
     return x < y + nb && y < x + na;
 }
 
+// Scratch of lc_relin_noalloc: a fixed device array (every GPU the library
+// runs on holds its own copy from module load until the process ends).  In
+// host code `scratch` names a host-side stand-in, never device memory: the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current (scratch_init, called by lc_ctx_create) and kept in
+// g_scratch.  Only those addresses are passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)LC_NOALLOC_SCRATCH_MIB << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) u64 scratch[NOALLOC_SCRATCH_BYTES / sizeof(u64)];
+static std::mutex g_scratch_mu;
+static u64 *g_scratch[MAX_DEVICES] = {};
+
+static int scratch_init(Ctx *c)
+{
+    if (c->device < 0 || c->device >= MAX_DEVICES) return fail(c, LC_EUNSUP, "device index outside 0..63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[c->device]) return LC_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(c, LC_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch[c->device] = (u64 *)p;
+    return LC_OK;
+}
+
+static u64 *scratch_of(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < MAX_DEVICES ? g_scratch[device] : nullptr;
+}
+
 static Ctx *C(lc_ctx *x) { return x ? &x->c : nullptr; }
 static const Ctx *C(const lc_ctx *x) { return x ? &x->c : nullptr; }
 
@@ -145,6 +177,7 @@ int lc_ctx_create(const lc_params *prm, int device, int role, lc_ctx **out)
         return LC_EHIP;
     }
     int rc = build_params(&x->c, prm);
+    if (!rc && device >= 0) rc = scratch_init(&x->c);  // with the device current
     if (rc) {
         lc_ctx_destroy(x);
         return rc;
@@ -591,6 +624,33 @@ int lc_relin(lc_ctx *x, const uint64_t *ct3, uint64_t *ct2, size_t count, void *
     g.out = ct2;
     g.out_stride = 2 * S;
     return keyswitch_hoisted(c, ct3 + 2 * S, 3 * S, count, &g, 1, (hipStream_t)stream);
+}
+
+int lc_relin_noalloc(lc_ctx *x, const uint64_t *ct3, uint64_t *ct2, size_t count, void *stream)
+{
+    CHECK_CTX(x);
+    if (!c->rlk) return fail(c, LC_EKEY, "no relinearization key");
+    const u64 per_ct = ks_words_per_ct(c);
+    if (per_ct * sizeof(u64) > NOALLOC_SCRATCH_BYTES)
+        return fail(c, LC_EINVAL, "one ciphertext's key-switch scratch (" + std::to_string(per_ct * sizeof(u64)) +
+                                      " bytes) exceeds the fixed " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                      "-byte array of lc_relin_noalloc");
+    if (!count) return LC_OK;
+    if (!ct3 || !ct2) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    if (overlap(ct3, count * 3 * S * 8, ct2, count * 2 * S * 8))
+        return fail(c, LC_EINVAL, "lc_relin_noalloc output must not overlap its input");
+    u64 *ws = scratch_of(c->device);
+    if (!ws) return fail(c, LC_EHIP, "no scratch address for this device");
+    KsGroup g{};
+    g.keys[0] = c->rlk;
+    g.n = 1;
+    g.base = ct3;
+    g.base_stride = 3 * S;
+    g.out = ct2;
+    g.out_stride = 2 * S;
+    return keyswitch_hoisted_ws(c, ct3 + 2 * S, 3 * S, count, &g, 1, ws, NOALLOC_SCRATCH_BYTES / sizeof(u64),
+                                (hipStream_t)stream);
 }
 
 int lc_rotate_hoisted(lc_ctx *x, const uint64_t *ct, size_t count, const int *steps, int nsteps, uint64_t *outs,

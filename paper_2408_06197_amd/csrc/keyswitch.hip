@@ -576,8 +576,6 @@ u64 ks_words_per_ct(const Ctx *c)
 int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
                       hipStream_t s)
 {
-    const u64 N = c->N;
-    const int nq = c->nq, np = c->np, ne = c->ne, dnum = c->dnum;
     for (int g = 0; g < ngroups; g++)
         if (groups[g].n < 1 || groups[g].n > 8) return fail(c, LC_EINVAL, "1..8 keys per hoisted group");
     const u64 per_ct = ks_words_per_ct(c);
@@ -585,6 +583,19 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
     if (c->ws_limit) chunk = std::max<u64>(1, std::min<u64>(chunk, c->ws_limit / (per_ct * 8)));
     u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk, s);
     if (!ws) return LC_ENOMEM;
+    return keyswitch_hoisted_ws(c, x, x_stride, count, groups, ngroups, ws, per_ct * chunk, s);
+}
+
+int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
+                         u64 *ws, u64 ws_words, hipStream_t s)
+{
+    const u64 N = c->N;
+    const int nq = c->nq, np = c->np, ne = c->ne, dnum = c->dnum;
+    for (int g = 0; g < ngroups; g++)
+        if (groups[g].n < 1 || groups[g].n > 8) return fail(c, LC_EINVAL, "1..8 keys per hoisted group");
+    const u64 per_ct = ks_words_per_ct(c);
+    if (ws_words < per_ct) return fail(c, LC_EINVAL, "key-switch scratch smaller than one ciphertext's");
+    const u64 chunk = std::min<u64>(std::min<u64>(count, (u64)c->tune.ks_chunk), ws_words / per_ct);
     int rc;
     for (u64 b0 = 0; b0 < count; b0 += chunk) {
         u64 B = std::min(chunk, count - b0);

@@ -289,6 +289,10 @@ struct KsGroup {
 // every group on it.
 int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
                       hipStream_t s);
+// The same with caller-provided scratch of ws_words words (at least
+// ks_words_per_ct); batches are sized to fit it.  Allocates nothing.
+int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
+                         u64 *ws, u64 ws_words, hipStream_t s);
 u64 ks_words_per_ct(const Ctx *c);
 // Builds (once, at key set-up: it copies to the device synchronously) the
 // tile-cycle walk of Galois element g.

@@ -74,6 +74,7 @@ _SIGS = {
     "lc_ct_mul": [VP, VP, VP, VP, SZ, VP],
     "lc_ct_square": [VP, VP, VP, SZ, VP],
     "lc_relin": [VP, VP, VP, SZ, VP],
+    "lc_relin_noalloc": [VP, VP, VP, SZ, VP],
     "lc_rotate_hoisted": [VP, VP, SZ, PINT, INT, VP, VP],
     "lc_rotate_sum": [VP, VP, SZ, PINT, INT, VP],
     "lc_mul_plain": [VP, VP, VP, VP, SZ, VP],
@@ -345,6 +346,13 @@ class Context:
         count = ct3.numel() // self.ct_words(3)
         out = self.empty(count, 2, self.nq, self.N) if out is None else out
         self._check(lib().lc_relin(self._h, _ptr(ct3), _ptr(out), count, _stream(stream)))
+        return out
+
+    def relin_noalloc(self, ct3, out, stream=None):
+        """lc_relin_noalloc: relinearization with the library's fixed scratch
+        array (no device allocation; `out` must be given)."""
+        count = ct3.numel() // self.ct_words(3)
+        self._check(lib().lc_relin_noalloc(self._h, _ptr(ct3), _ptr(out), count, _stream(stream)))
         return out
 
     def rotate_hoisted(self, ct, steps, out=None, stream=None):
