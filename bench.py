@@ -39,13 +39,22 @@ A2_OPS_PER_UPDATE = 23
 # kernel source it was taken on: the section of ops.hip is hashed at run time.
 A2_PMC = {"fetch_bytes": 2.0 * 84056231 * 1024, "write_bytes": 7004160 * 1024,
           "source_sha256": "2922c9900c02ddf658ce4917553015c79efdfb4ab2f23ce688a97d7ba92298fd"}
+A2_SECTION = ("ops.hip", "// ---- fused subtract / square / lazy accumulate over all pairs", "// ---- SumDis[i]")
+# The same for the forward NTT's two launches on 64 ciphertexts' limbs
+# (1536 limb-polynomials at N = 2^16): `python -m
+# paper_2408_06197_amd.profile_cases ntt`, per-launch averages of the forward
+# passes; see profiles/ntt_fwd_n65536_l24_64cts_pmc.txt.  Empty until taken.
+NTT_SECTION = ("ntt.hip", "// ---- register-radix pass kernel", "struct FastPass {")
+NTT_PMC = {"fetch_bytes_per_launch": 2.0 * (393370 + 399435) / 2 * 1024, "write_bytes_per_launch": 786432 * 1024,
+           "limb_polys": 1536,
+           "source_sha256": "cad1c356dc5ce9acd6799f0b55d87fc152e3991aaebc8179575cdf987050a575"}
 
 
-def _a2_source_sha256():
+def _source_sha256(fname, start, stop):
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2408_06197_amd", "csrc", "ops.hip")).read()
-    a = src.index("// ---- fused subtract / square / lazy accumulate over all pairs")
-    b = src.index("// ---- SumDis[i]")
+    src = open(os.path.join(ROOT, "paper_2408_06197_amd", "csrc", fname)).read()
+    a = src.index(start)
+    b = src.index(stop)
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
@@ -64,7 +73,6 @@ def parse():
                    help="skip the launch-shape / plan autotuner")
     p.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    p.add_argument("--oracle-cts", type=int, default=4, help="packed ciphertexts in the oracle's sample pair")
     p.add_argument("--per-op-pairs", type=int, default=2, help="pairs timed in the plain per-op form (0: skip)")
     p.add_argument("--no-graph", dest="graph", action="store_false", default=True,
                    help="time eager launches instead of a captured HIP graph")
@@ -74,8 +82,10 @@ def parse():
                    help="skip the lazy/eager relinearization and per-client SumDis ablations")
     p.add_argument("--no-ntt-micro", dest="ntt_micro", action="store_false", default=True,
                    help="skip the mixed-degree NTT / hoisted key-switch micro-workload")
-    p.add_argument("--serve", type=int, default=0, metavar="ROUNDS",
-                   help="also run the serving form: ROUNDS Poisson-arriving aggregation rounds")
+    p.add_argument("--serve", type=int, default=100, metavar="ROUNDS",
+                   help="serving form: ROUNDS Poisson-arriving aggregation rounds (0: skip)")
+    p.add_argument("--no-small-configs", dest="small_configs", action="store_false", default=True,
+                   help="skip the N=2^12 and N=2^14 workloads (batched, per-op and eager forms)")
     p.add_argument("--serve-slots", type=int, default=4)
     p.add_argument("--sweep-n", dest="sweep_n", action="store_true", default=False,
                    help="also run the packing-size sweep N = 2^13..2^17 on the depth-3 parameters")
@@ -110,9 +120,10 @@ def ntt_roofline(torch, srv, batch):
     two launches (passes) per transform, each with 8 N bytes of algorithmic
     traffic per limb-polynomial (the transform's one read plus one write,
     16 N bytes, split over its two launches)."""
-    x = torch.randint(0, 1 << 40, (batch, srv.nq, srv.N), dtype=torch.int64, device="cuda")
-    # residues must be below every q: 2^40 < 2^49 <= q_l
-    ms = event_time(torch, lambda: srv.ntt_fwd(x, nlimb=srv.nq), reps=5)
+    import synth
+    x = synth.device_residues_mod(torch, 1717, srv.q, (batch, srv.nq, srv.N))
+    s = torch.cuda.current_stream()
+    ms = event_time(torch, lambda: srv.ntt_fwd(x, nlimb=srv.nq, stream=s), reps=5)
     npoly = batch * srv.nq
     launches = 2
     per_launch_ms = ms / launches
@@ -156,11 +167,28 @@ def d4_polys(torch, ctxs, seed):
 
 
 def d4_ntt(ctxs, polys, inverse=False):
+    """One context per degree, two launches per degree and tail."""
     for ctx, (x, y) in zip(ctxs, polys):
         f = ctx.ntt_inv if inverse else ctx.ntt_fwd
         f(x, nlimb=x.shape[1])
         if y is not None:
             f(y, nlimb=y.shape[1])
+
+
+def d4_groups(polys):
+    """The micro-workload as polynomial groups of one mixed-degree call."""
+    g = []
+    for (x, y), (ln, _, nq, _) in zip(polys, D4):
+        g.append((x, ln, nq, 0))
+        if y is not None:
+            g.append((y, ln, y.shape[1], 0))
+    return g
+
+
+def d4_ntt_mixed(big, polys, inverse=False):
+    """All 4096 polynomials in one launch per pass on the degree-2^16 context
+    (whose chain starts with the smaller degrees' primes)."""
+    (big.ntt_inv_groups if inverse else big.ntt_fwd_groups)(d4_groups(polys))
 
 
 def d4_rotation_steps(log_n):
@@ -177,28 +205,33 @@ def ntt_micro(torch, L):
     keep = [(x.clone(), None if y is None else y.clone()) for x, y in polys]
     alg_bytes = sum(cnt * (1 << ln) * 16 for ln, cnt, _, _ in D4)
     res = {"polys": {str(1 << ln): cnt for ln, cnt, _, _ in D4}, "algorithmic_bytes_per_direction": alg_bytes}
-    best = None
-    for sub in (0, 32768, 65536):
-        for c in ctxs:
-            c.set_tuning("ntt_sub_kb", sub)
-        fwd = event_time(torch, lambda: d4_ntt(ctxs, polys), reps=3)
-        inv = event_time(torch, lambda: d4_ntt(ctxs, polys, inverse=True), reps=3)
-        res.setdefault("fwd_ms_by_ntt_sub_kb", {})[str(sub)] = fwd
-        res.setdefault("inv_ms_by_ntt_sub_kb", {})[str(sub)] = inv
-        if best is None or fwd + inv < best[0] + best[1]:
-            best = (fwd, inv, sub)
-    for c in ctxs:
-        c.set_tuning("ntt_sub_kb", best[2])
+    # one launch per pass over every polynomial of every degree (the
+    # degree-2^16 context's chain starts with the smaller contexts' primes)
+    big = ctxs[-1]
+    assert big.moduli[:3] == ctxs[0].moduli[:3] and big.moduli[:6] == ctxs[1].moduli[:6]
+    fwd = event_time(torch, lambda: d4_ntt_mixed(big, polys), reps=3)
+    inv = event_time(torch, lambda: d4_ntt_mixed(big, polys, inverse=True), reps=3)
+    # the same transforms as per-degree launches (six calls of two passes)
+    res["per_degree_fwd_ms"] = event_time(torch, lambda: d4_ntt(ctxs, polys), reps=3)
+    res["per_degree_inv_ms"] = event_time(torch, lambda: d4_ntt(ctxs, polys, inverse=True), reps=3)
     torch.cuda.synchronize()
     # the timed transforms ran in forward/inverse pairs: the data is back
     res["round_trip_exact"] = all(bool(torch.equal(x, a)) and (y is None or bool(torch.equal(y, b)))
                                   for (x, y), (a, b) in zip(polys, keep))
-    fwd, inv = best[0], best[1]
-    res.update({"ntt_sub_kb": best[2], "fwd_ms": fwd, "inv_ms": inv,
+    # and the mixed call gives the per-degree contexts' bits
+    d4_ntt_mixed(big, polys)
+    ref = [(x.clone(), None if y is None else y.clone()) for x, y in keep]
+    d4_ntt(ctxs, ref)
+    res["mixed_equals_per_degree"] = all(bool(torch.equal(x, a)) and (y is None or bool(torch.equal(y, b)))
+                                         for (x, y), (a, b) in zip(polys, ref))
+    d4_ntt_mixed(big, polys, inverse=True)
+    del ref
+    res.update({"launches_per_direction": 2, "fwd_ms": fwd, "inv_ms": inv,
                 "fwd_GBps": alg_bytes / (fwd / 1e3) / 1e9, "inv_GBps": alg_bytes / (inv / 1e3) / 1e9})
-    log(f"[bench] NTT micro (2341x2^12 + 1170x2^14 + 585x2^16): fwd {fwd:.2f} ms ({res['fwd_GBps']:.0f} GB/s), "
-        f"inv {inv:.2f} ms ({res['inv_GBps']:.0f} GB/s), sub-batch {best[2]} KiB, round trip "
-        f"{'exact' if res['round_trip_exact'] else 'MISMATCH'}")
+    log(f"[bench] NTT micro (2341x2^12 + 1170x2^14 + 585x2^16, one launch per pass): fwd {fwd:.2f} ms "
+        f"({res['fwd_GBps']:.0f} GB/s), inv {inv:.2f} ms ({res['inv_GBps']:.0f} GB/s); per-degree launches "
+        f"{res['per_degree_fwd_ms']:.2f} / {res['per_degree_inv_ms']:.2f} ms; round trip "
+        f"{'exact' if res['round_trip_exact'] else 'MISMATCH'}, mixed == per-degree: {res['mixed_equals_per_degree']}")
     del keep
     ks = {}
     for ctx, (x, _), (ln, cnt, nq, k) in zip(ctxs, polys, D4):
@@ -225,46 +258,212 @@ def ntt_micro(torch, L):
     return res
 
 
-def cpu_baseline(w, plan, n_cts, min_seconds=12.0):
-    """The oracle on the host cores: client pairs (0, n-1), (1, n-2), ... each
-    with n_cts packed ciphertexts in the tensor phase (scaled linearly to the
-    full LEN), one relinearization and the full rotate-and-sum, until at least
-    min_seconds of oracle time; reported as distances/s."""
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _omp_threads(k):
+    """Thread count of the oracle's OpenMP regions (libgomp, as the oracle is
+    built with gcc -fopenmp); None if it cannot be set."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+        return int(k)
+    except OSError:
+        return None
+
+
+def _oracle_keys(O, w, plan):
+    ora = O.Oracle(w.log_n, w.q_bits, w.p_bits)
+    s = ora.secret(w.crypto_seed)
+    rlk = ora.relin_key(w.crypto_seed, s)
+    rks = [ora.rot_key(w.crypto_seed, s, k) for k in ora.rotsum_steps(plan)]
+    return ora, s, rlk, rks
+
+
+def _oracle_pair(ora, cts, rlk, plan, rks):
+    """Times (tensor phase, relinearization, rotate-and-sum) of one pair."""
+    t0 = time.perf_counter()
+    tri = ora.pair_triple(cts, 0, 1)
+    t1 = time.perf_counter()
+    d = ora.relin(tri, rlk)
+    t2 = time.perf_counter()
+    ora.rotate_sum(d, plan, rks)
+    t3 = time.perf_counter()
+    return t1 - t0, t2 - t1, t3 - t2
+
+
+def cpu_baseline(w, plan, small_plans):
+    """The oracle on the host cores (all of them, then one thread on a
+    sample), reported as client-pair distances/s:
+      * the N = 2^16 workload: one whole client pair -- the tensor phase over
+        all LEN packed ciphertexts, one relinearization and the rotate-and-sum
+        with the bench's plan -- with no scaling; the inputs are synthetic
+        residues (16 random packed ciphertexts per client repeated to LEN:
+        the oracle's work does not depend on the values);
+      * one thread: the same pair's relinearization and the tensor phase over
+        16 packed ciphertexts, against the same sample on all threads;
+      * the N = 2^12 and N = 2^14 workloads in full (every pair, real
+        encryptions), distances checked against FP64.
+    Key generation is set-up and is not timed."""
     from oracle import oracle as O
     import synth
 
-    ora = O.Oracle(w.log_n, w.q_bits, w.p_bits)
-    seed = w.crypto_seed
-    s = ora.secret(seed)
-    pk = ora.pk(seed, s)
-    rlk = ora.relin_key(seed, s)
-    rks = [ora.rot_key(seed, s, k) for k in ora.rotsum_steps(plan)]
-    scale = 2.0 ** w.scale_log2
-    k = min(n_cts, w.n_ct)
-    per_pair, spent, pairs = [], 0.0, []
-    for a in range(w.n_clients // 2):
-        b = w.n_clients - 1 - a
-        upd = synth.client_updates(w, clients=[a, b])
-        m = np.stack([np.stack([O.encode(c, w.log_n, scale) for c in synth.pack(u, w.slots)[:k]]) for u in upd])
-        cts = ora.encrypt(seed + 1, 0, m.reshape(2 * k, w.N), pk).reshape(2, k, 2, ora.nq, w.N)
+    cpu = host_cpu()
+    threads = _omp_threads(cpu["nproc"])
+    ora, s, rlk, rks = _oracle_keys(O, w, plan)
+    block = synth.uniform_residues(77, ora.q, (2, 16, 2, w.N))
+    cts = np.empty((2, w.n_ct) + block.shape[2:], dtype=np.uint64)
+    for k0 in range(0, w.n_ct, 16):
+        k = min(16, w.n_ct - k0)
+        cts[:, k0:k0 + k] = block[:, :k]
+    del block
+    t_tensor, t_relin, t_rot = _oracle_pair(ora, cts, rlk, plan, rks)
+    sec = t_tensor + t_relin + t_rot
+    # one thread against all threads on a sample of the same pair
+    sample = np.ascontiguousarray(cts[:, :16])
+    del cts
+    t_all = sum(_oracle_pair(ora, sample, rlk, plan, rks)[:2])
+    one = _omp_threads(1)
+    t_one = sum(_oracle_pair(ora, sample, rlk, plan, rks)[:2]) if one else None
+    _omp_threads(cpu["nproc"])
+    del sample
+    full = {}
+    for sw, pl in small_plans:
         t0 = time.perf_counter()
-        tri = ora.pair_triple(cts, 0, 1)
+        o2, s2, rlk2, rks2 = _oracle_keys(O, sw, pl)
+        pk2 = o2.pk(sw.crypto_seed, s2)
+        upd = synth.client_updates(sw)
+        scale = 2.0 ** sw.scale_log2
+        m = np.stack([np.stack([O.encode(c, sw.log_n, scale) for c in synth.pack(u, sw.slots)]) for u in upd])
+        n, ln = m.shape[:2]
+        c2 = o2.encrypt(sw.crypto_seed + 1, 0, m.reshape(n * ln, sw.N), pk2).reshape(n, ln, 2, o2.nq, sw.N)
+        t_setup = time.perf_counter() - t0
         t1 = time.perf_counter()
-        d = ora.relin(tri, rlk)
-        ora.rotate_sum(d, plan, rks)
-        t3 = time.perf_counter()
-        per_pair.append((t1 - t0) * w.n_ct / k + (t3 - t1))
-        spent += t3 - t0
-        pairs.append((a, b))
-        if spent >= min_seconds:
-            break
-    sec = float(np.mean(per_pair))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / sec, "unit": "client-pair distances/s", "cores": cores, "kind": "oracle",
-            "sample": "%d client pairs %s: tensor phase over %d of %d packed ciphertexts scaled x%.2f, plus one "
-                      "relinearization and the rotate-and-sum (plan %s) measured whole; %.1f s of oracle time"
-                      % (len(pairs), pairs, k, w.n_ct, w.n_ct / k, ",".join(map(str, plan)), spent),
-            "seconds_per_pair": sec}
+        res = o2.pairwise(c2, rlk2, pl, rks2, want_sumdis=False)
+        t_run = time.perf_counter() - t1
+        got = np.array([o2.read_distance(o2.decrypt(d, s2), scale * scale) for d in res["dist"]])
+        ref = fp64_pair_distances(upd)
+        full[sw.name] = {"pairs": sw.n_pairs, "plan": pl, "seconds": t_run, "distances_per_s": sw.n_pairs / t_run,
+                         "setup_s_untimed": t_setup,
+                         "max_rel_err_vs_fp64": float(np.max(np.abs(got - ref) / np.abs(ref)))}
+        log(f"[bench] oracle {sw.name}: {sw.n_pairs} pairs in {t_run:.1f}s ({sw.n_pairs / t_run:.2f} distances/s)")
+    return {"value": 1.0 / sec, "unit": "client-pair distances/s", "cores": threads or cpu["nproc"],
+            "kind": "oracle",
+            "sample": "one whole client pair of the %s workload, not scaled: tensor phase over all %d packed "
+                      "ciphertexts (%.1f s), one relinearization (%.1f s), rotate-and-sum with plan %s (%.1f s); "
+                      "synthetic residues (16 random packed ciphertexts per client repeated to %d)"
+                      % (w.name, w.n_ct, t_tensor, t_relin, ",".join(map(str, plan)), t_rot, w.n_ct),
+            "seconds_per_pair": sec, "cpu": cpu,
+            "one_thread": {"sample": "tensor phase over 16 packed ciphertexts + one relinearization",
+                           "seconds": t_one, "seconds_all_threads": t_all,
+                           "speedup_all_threads": (t_one / t_all) if t_one else None},
+            "full_configs": full}
+
+
+def plans_for(log_n):
+    levels = log_n - 1
+    return [[1] * levels, [2] * (levels // 2) + [1] * (levels % 2), [3] * (levels // 3) + ([levels % 3] if levels % 3 else [])]
+
+
+def small_config(torch, L, synth, w):
+    """A smaller workload at full size on the GPU, in every form: device
+    ingest; the batched pipeline (lc_pairwise_sqdist) under each hoisting
+    plan; the plain per-op launch form over every pair (lc_ct_sub,
+    lc_ct_square and lc_ct_add per packed ciphertext, then lc_relin and
+    lc_rotate_sum per pair); the eager-relinearization form (a
+    relinearization per packed ciphertext, Table 2's "without lazy
+    relinearization"); per-client SumDis (lc_sumdis_lazy).  Every form's
+    decrypted distances are checked against FP64."""
+    n, ln, N, P = w.n_clients, w.n_ct, w.N, w.n_pairs
+    scale = 2.0 ** w.scale_log2
+    plans = plans_for(w.log_n)
+    kgc = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_KGC)
+    srv = L.Context(w.log_n, w.q_bits, w.p_bits, device=0, role=L.ROLE_SERVER)
+    kgc.keygen(w.crypto_seed)
+    kgc.keygen_rotation(w.crypto_seed, sorted({s_ for pl in plans for s_ in kgc.rotsum_steps(pl)}))
+    kgc.keys_share(srv)
+    upd = synth.client_updates(w)
+    ref = fp64_pair_distances(upd)
+    nq = srv.nq
+    cts = torch.empty((n, ln, 2, nq, N), dtype=torch.int64, device="cuda")
+    for i in range(n):
+        z = torch.from_numpy(synth.pack(upd[i], w.slots)).cuda()
+        srv.encrypt(srv.encode_device(z, scale), seed=w.crypto_seed + 1, first_object=i * ln, out=cts[i])
+    dist = torch.empty((P, 2, nq, N), dtype=torch.int64, device="cuda")
+
+    def rel_err(d):
+        dec = kgc.decrypt(d)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()
+        got = kgc.crt_to_double(dec) / scale ** 2
+        return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+    res = {"N": N, "limbs": nq, "clients": n, "ciphertexts_per_client": ln, "pairs": P}
+    best = None
+    for pl in plans:
+        ms = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=pl, out=dist), reps=3)
+        res.setdefault("batched_ms_by_plan", {})[",".join(map(str, pl))] = ms
+        if best is None or ms < best[0]:
+            best = (ms, pl)
+    ms, plan = best
+    srv.pairwise_sqdist(cts, plan=plan, out=dist)
+    res["batched"] = {"plan": plan, "ms": ms, "distances_per_s": P / (ms / 1e3), "max_rel_err_vs_fp64": rel_err(dist)}
+    pidx = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    tmp = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+    sq = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+    acc3 = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
+    acc2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+    r2 = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
+    out = torch.empty((P, 2, nq, N), dtype=torch.int64, device="cuda")
+
+    def per_op(eager):
+        for p_, (a, b) in enumerate(pidx):
+            (acc2 if eager else acc3).zero_()
+            for k in range(ln):
+                srv.ct_sub(cts[a, k], cts[b, k], out=tmp)
+                srv.ct_square(tmp, out=sq)
+                if eager:
+                    srv.relin(sq, out=r2)
+                    srv.ct_add(acc2, r2, out=acc2)
+                else:
+                    srv.ct_add(acc3, sq, out=acc3, ncomp=3)
+            if eager:
+                out[p_].copy_(acc2[0])
+            else:
+                srv.relin(acc3, out=out[p_:p_ + 1])
+            srv.rotate_sum(out[p_:p_ + 1], plan)
+
+    for name, eager in (("per_op_lazy", False), ("per_op_eager", True)):
+        t = event_time(torch, lambda: per_op(eager))
+        res[name] = {"ms": t, "distances_per_s": P / (t / 1e3), "max_rel_err_vs_fp64": rel_err(out),
+                     "key_switches_per_pair": (ln if eager else 1) + len(plan)}
+    res["lazy_vs_eager_speedup"] = res["per_op_eager"]["ms"] / res["per_op_lazy"]["ms"]
+    res["batched_vs_per_op_speedup"] = res["per_op_lazy"]["ms"] / res["batched"]["ms"]
+    sd = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
+    t_sd = event_time(torch, lambda: srv.sumdis_lazy(cts, plan=plan, out=sd), reps=3)
+    dec = kgc.decrypt(sd)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()
+    D = np.zeros((n, n))
+    for p_, (a, b) in enumerate(pidx):
+        D[a, b] = D[b, a] = ref[p_]
+    got = kgc.crt_to_double(dec) / scale ** 2
+    res["sumdis_per_client"] = {"ms": t_sd, "key_switch_chains": n,
+                                "max_rel_err_vs_fp64": float(np.max(np.abs(got - D.sum(1)) / D.sum(1)))}
+    log(f"[bench] {w.name}: batched {ms:.2f} ms ({P / (ms / 1e3):.0f} distances/s, plan {plan}); per-op "
+        f"{res['per_op_lazy']['ms']:.1f} ms, eager relin {res['per_op_eager']['ms']:.1f} ms "
+        f"({res['lazy_vs_eager_speedup']:.1f}x); max rel err {res['batched']['max_rel_err_vs_fp64']:.1e}")
+    del cts, dist, out, sd
+    for c in (srv, kgc):
+        c.release_workspace()
+    return res
 
 
 def sweep_n(torch, L, synth, log_ns=(13, 14, 15, 16, 17), dim=11_200_000, n=20, steps=2):
@@ -342,10 +541,11 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     import synth
 
     w14, w16 = synth.CFG2, synth.CFG3
-    chains = {"n16384_l8": serve.ChainInfo("n16384_l8", 14, 8, 2, 40),
-              "n65536_l24": serve.ChainInfo("n65536_l24", 16, 24, 4, 40)}
     kgc14 = L.Context(w14.log_n, w14.q_bits, w14.p_bits, device=0, role=L.ROLE_KGC)
     srv14 = L.Context(w14.log_n, w14.q_bits, w14.p_bits, device=0, role=L.ROLE_SERVER)
+    # rounds are sized by lc_footprint of the server contexts
+    chains = {"n16384_l8": serve.ChainInfo("n16384_l8", 14, 8, 2, 40, ctx=srv14),
+              "n65536_l24": serve.ChainInfo("n65536_l24", 16, 24, 4, 40, ctx=srv16)}
     plan14 = [3] * 4 + [1]
     kgc14.keygen(w14.crypto_seed)
     kgc14.keygen_rotation(w14.crypto_seed, kgc14.rotsum_steps(plan14))
@@ -365,10 +565,10 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     log(f"[bench] serving: pools encoded in {time.perf_counter() - t0:.1f}s")
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    # leave room for the library's per-stream scratch at N=2^16 (key-switch
-    # batch of 32: 5 GB; rotation ping-pong and encryption staging: up to
-    # 3 GB) and for torch's cache
-    budget = int(0.5 * (free - args.serve_slots * 8 * 2 ** 30))
+    # leave room for the library's per-stream workspace (the largest a stream
+    # can grow for 40-client rounds, lc_footprint) and for torch's cache
+    ws = max(serve.stream_workspace(ch, 40, k_chunk) for ch in chains.values())
+    budget = int(0.5 * (free - args.serve_slots * ws))
     names = list(chains)
 
     def progress(k, rec):
@@ -403,13 +603,25 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
         ref = serve.reference_distances(sp, pools[sp.chain], chains[sp.chain].n_ct(sp.dim))
         got = rec[rid]["result"]["distances"]
         errs.append(float(np.max(np.abs(got - ref) / np.abs(ref))))
+    by_class = serve.latency_by_class(rec)
+    # the rounds behind the tail: the slowest 2% and their classes
+    slow = sorted(rec.values(), key=lambda r: -r["latency"])[: max(1, len(rec) // 50)]
     st.update({"wall_s": wall, "slots": args.serve_slots, "k_chunk": k_chunk, "budget_bytes": budget,
-               "rate_per_s": rate, "calibrated_capacity_per_s": capacity, "checked_rounds": len(errs),
-               "max_rel_err_vs_fp64": max(errs) if errs else None,
+               "stream_workspace_bytes": ws, "rate_per_s": rate, "calibrated_capacity_per_s": capacity,
+               "checked_rounds": len(errs), "max_rel_err_vs_fp64": max(errs) if errs else None,
+               "resident_rounds": sum(1 for r in rec.values() if chains[r["chain"]].n_ct(r["dim"]) <= k_chunk),
                "by_chain": {c: serve.latency_stats({k: v for k, v in rec.items() if v["chain"] == c})
-                            for c in names if any(v["chain"] == c for v in rec.values())}})
+                            for c in names if any(v["chain"] == c for v in rec.values())},
+               "by_class": by_class,
+               "slowest": [{"rid": r["rid"], "chain": r["chain"], "n": r["n"], "dim": r["dim"],
+                            "latency_s": r["latency"], "queue_s": r["admit"] - r["arrival"],
+                            "service_s": r["done"] - r["admit"]} for r in slow]})
     log(f"[bench] serving: {st['rounds']} rounds in {wall:.1f}s, {st['rounds_per_s']:.2f} rounds/s, "
-        f"p50 {st['p50_s']:.3f}s p99 {st['p99_s']:.3f}s, max rel err {st['max_rel_err_vs_fp64']}")
+        f"{st['distances_per_s']:.1f} distances/s, p50 {st['p50_s']:.3f}s p99 {st['p99_s']:.3f}s (mean queue "
+        f"{st['mean_queue_s']:.3f}s, service {st['mean_service_s']:.3f}s), max rel err {st['max_rel_err_vs_fp64']}")
+    for r in st["slowest"]:
+        log(f"[bench] serving tail: round {r['rid']} {r['chain']} n={r['n']} dim={r['dim']}: "
+            f"{r['latency_s']:.2f}s = queue {r['queue_s']:.2f}s + service {r['service_s']:.2f}s")
     return st
 
 
@@ -739,25 +951,11 @@ def main():
                                        "key_switches_eager": ln + len(plan), "key_switches_lazy": 1 + len(plan),
                                        "distance_eager": d_e, "distance_lazy": d_l}
         del tmp, sq, r2, acc2, acc3, out2
-        # SumDis with one relinearization and rotate-and-sum per client: the
-        # triples of all pairs (i, j) are summed per client i first (n key
-        # switch chains instead of P)
-        trip = torch.empty((P, 3, nq, N), dtype=torch.int64, device="cuda")
-        sums = torch.empty((n, 3, nq, N), dtype=torch.int64, device="cuda")
+        # SumDis with one relinearization and rotate-and-sum per client
+        # (lc_sumdis_lazy): the triples of all pairs (i, j) are summed per
+        # client i first (n key-switch chains instead of P)
         s2 = torch.empty((n, 2, nq, N), dtype=torch.int64, device="cuda")
-        pidx = [(a, b) for a in range(n) for b in range(a + 1, n)]
-
-        def sumdis_lazy():
-            srv.pair_triples(cts, out=trip)
-            sums.zero_()
-            for p_, (a, b) in enumerate(pidx):
-                srv.ct_add(sums[a], trip[p_], out=sums[a], ncomp=3)
-                srv.ct_add(sums[b], trip[p_], out=sums[b], ncomp=3)
-            srv.relin(sums, out=s2)
-            srv.rotate_sum(s2, plan)
-
-        t_sd = event_time(torch, sumdis_lazy)
-        del trip, sums
+        t_sd = event_time(torch, lambda: srv.sumdis_lazy(cts, plan=plan, out=s2))
         t_full = extra["stage_ms"]["pairwise_total"] if "stage_ms" in extra else None
         ds = kgc.crt_to_double(kgc.decrypt(s2)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()) / scale ** 2
         dref = kgc.crt_to_double(kgc.decrypt(sumdis)[:, :, 0].cpu().numpy().view(np.uint64).T.copy()) / scale ** 2
@@ -774,8 +972,11 @@ def main():
     # Candidates: the fused pair-triple kernel (one launch per step, FP64-ALU
     # bound: 23 FP64 lane-instructions per update in the Barrett form -- two
     # subtractions, three products of six instructions, three accumulations)
-    # and the NTT passes of the key switches (HBM bound).  The one with the
-    # larger share of the step is reported.
+    # and the NTT passes of the key switches (HBM bound; the figure is one
+    # forward transform of 64 ciphertexts' limbs, timed, over its two
+    # launches, and its share of the step is that time per limb-transform
+    # times the limb-transforms a step performs).  The `roofline` entry is
+    # the candidate with the larger estimated share of the step.
     roof = None
     if args.stages:
         nt = ntt_roofline(torch, srv, 64 if w.log_n >= 15 else 256)
@@ -797,19 +998,23 @@ def main():
                   "launch_ms": extra["stage_ms"]["pair_triples"], "est_ms_per_step": extra["stage_ms"]["pair_triples"]}
         ntt = {"bound": "hbm", "achieved": nt["bytes_per_launch"] / (nt["launch_ms"] / 1e3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "kernel": "ntt_fast_kernel",
-               "units_per_launch": "%d limb-polys x 8N bytes" % nt["limb_polys"], "launch_ms": nt["launch_ms"],
-               "est_ms_per_step": ntt_ms_step}
+               "units_per_launch": "%d limb-polys x 8N bytes (16N per transform over its two launches)"
+                                   % nt["limb_polys"],
+               "launch_ms": nt["launch_ms"], "est_ms_per_step": ntt_ms_step}
         for r in (a2, ntt):
             r["frac"] = r["achieved"] / r["peak"]
-        if not tuned.get("pair_mfma") and A2_PMC["source_sha256"] == _a2_source_sha256():
+        if not tuned.get("pair_mfma") and A2_PMC["source_sha256"] == _source_sha256(*A2_SECTION):
             a2["traffic"] = A2_PMC["fetch_bytes"] + A2_PMC["write_bytes"]
             a2["traffic_vs_algorithmic"] = a2["traffic"] / a2_bytes
-        # the pair-triple kernel is the step's largest single kernel (one
-        # launch); the NTT's share is spread over hundreds of launches
-        roof = a2
-        extra["kernels"] = {"pair_triples": a2, "ntt": ntt}
+        if NTT_PMC and NTT_PMC["source_sha256"] == _source_sha256(*NTT_SECTION) and nt["limb_polys"] == NTT_PMC["limb_polys"]:
+            ntt["traffic"] = NTT_PMC["fetch_bytes_per_launch"] + NTT_PMC["write_bytes_per_launch"]
+            ntt["traffic_vs_algorithmic"] = ntt["traffic"] / nt["bytes_per_launch"]
+            ntt["traffic_GBps"] = ntt["traffic"] / (nt["launch_ms"] / 1e3) / 1e9
+        roof = max((a2, ntt), key=lambda r: r["est_ms_per_step"])
+        extra["kernels"] = {"pair_triples": a2, "ntt": ntt, "reported": roof["kernel"]}
         log(f"[bench] a2 kernel {a2['launch_ms']:.1f} ms ({a2['achieved']:.2f} T FP64 ops/s, {a2['frac']:.1%} of VALU); "
-            f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step")
+            f"NTT {ntt['achieved']:.0f} GB/s per launch ({ntt['frac']:.1%} of HBM), ~{ntt_ms_step:.0f} ms/step; "
+            f"reported: {roof['kernel']}")
 
     # the round's ciphertexts are no longer needed
     used_graph = graph is not None
@@ -833,11 +1038,21 @@ def main():
         else:
             extra["serving"] = serve_bench(args, torch, L, srv, kgc, plan)
 
+    small_plans = []
+    if args.small_configs and w.log_n == 16:
+        extra["configs"] = {}
+        for sw in (synth.CFG1, synth.CFG2):
+            extra["configs"][sw.name] = small_config(torch, L, synth, sw)
+            small_plans.append((sw, extra["configs"][sw.name]["batched"]["plan"]))
+            torch.cuda.empty_cache()
+
     base = None
     if args.cpu_baseline:
-        log("[bench] timing the CPU oracle on a sample pair")
-        base = cpu_baseline(w, plan, args.oracle_cts)
-        log(f"[bench] oracle: {base['value']:.4f} distances/s ({base['sample']})")
+        log("[bench] timing the CPU oracle: one whole pair of this workload, the smaller workloads in full")
+        base = cpu_baseline(w, plan, small_plans)
+        log(f"[bench] oracle: {base['value']:.4f} distances/s ({base['sample']}); one thread "
+            f"{base['one_thread']['seconds']} s vs {base['one_thread']['seconds_all_threads']:.2f} s on "
+            f"{base['cores']} threads ({base['cpu']['model']})")
 
     out = {
         "metric": "encrypted client-pair distances/s at N=2^16",
