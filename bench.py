@@ -47,7 +47,7 @@ A2_SECTION = ("ops.hip", "// ---- fused subtract / square / lazy accumulate over
 NTT_SECTION = ("ntt.hip", "// ---- register-radix pass kernel", "struct FastPass {")
 NTT_PMC = {"fetch_bytes_per_launch": 2.0 * (393370 + 399435) / 2 * 1024, "write_bytes_per_launch": 786432 * 1024,
            "limb_polys": 1536,
-           "source_sha256": "cad1c356dc5ce9acd6799f0b55d87fc152e3991aaebc8179575cdf987050a575"}
+           "source_sha256": "a86d965bd578d5e3a3381f915880795e01d2f3d1237a77cc9cf6ee14348e5f94"}
 
 
 def _source_sha256(fname, start, stop):
@@ -758,12 +758,18 @@ def main():
                 bestm = (ms, shp)
         srv.set_tuning("ms_shape", bestm[1])
         tuned["ms_shape"] = bestm[1]
+        # (ks_chunk 192: every distance ciphertext in one key-switch batch, one
+        # launch per stage; each trial starts from released workspaces, so
+        # outgrown batches do not stay resident)
         for name, values in (("mac_cycle_short", (1, 0)), ("mac_cycle_cts", (8, 16)), ("mac_short_cts", (16, 8)),
                              ("mac_cycle_c0", (1, 0)),
                              ("mac_cts", (8, 16)),
-                             ("ks_chunk", (32, 64, 128))):
+                             ("ks_chunk", (32, 64, 128, 192)),
+                             ("ks_streams", (2, 1))):
             bestv = None
             for v in values:
+                if name in ("ks_chunk", "ks_streams"):
+                    srv.release_workspace()
                 srv.set_tuning(name, v)
                 ms = event_time(torch, lambda: srv.pairwise_sqdist(cts, plan=plan, out=dist))
                 tuned.setdefault(name + "_ms", {})[str(v)] = ms
@@ -771,6 +777,7 @@ def main():
                     bestv = (ms, v)
             srv.set_tuning(name, bestv[1])
             tuned[name] = bestv[1]
+        srv.release_workspace()
         log(f"[bench] autotuned: {tuned}")
 
     def step():

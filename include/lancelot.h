@@ -313,7 +313,7 @@ typedef struct lc_poly_group {
  * degree-2^k polynomial is transformed with psi_k, the smallest primitive
  * 2^(k+1)-th root of unity of its modulus, so its result equals lc_ntt_fwd /
  * lc_ntt_inv of a context of degree 2^k with the same moduli.  Needs
- * 12 <= log_n <= min(16, the context's log_n) (LC_EUNSUP) and 1 <= ngroups
+ * 12 <= log_n <= min(17, the context's log_n) (LC_EUNSUP) and 1 <= ngroups
  * <= 16 (LC_EINVAL); every modulus of the context is = 1 mod 2N, hence also
  * mod 2^(k+1).  The first call with a degree below the context's uploads that
  * degree's twiddle tables (synchronous). */
@@ -335,7 +335,7 @@ int lc_workspace_query(const lc_ctx *ctx, int n, int len, size_t *bytes);
  * LC_FP_SUMDIS the SumDis ciphertexts, LC_FP_PLAINTEXTS one chunk of int64
  * plaintexts to encrypt, LC_FP_DECRYPT the decrypted distances [P][n_q][N].
  * *workspace_bytes (may be NULL): the library workspace those calls grow on
- * the round's stream (kept by the stream afterwards).  LC_EINVAL for n < 2
+ * the round's stream and its second stream (kept by them afterwards).  LC_EINVAL for n < 2
  * or len < 1. */
 #define LC_FP_SUMDIS 1
 #define LC_FP_PLAINTEXTS 2
@@ -367,7 +367,11 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * "fuse_modup" (1 = for 2^10 <= N the ModUp base conversion runs inside the
  * first forward-NTT pass of the raised digits; 0 = a kernel of its own),
  * "ms_shape" (masked-sum lanes: 0 = 1 coefficient x 16 rows, 1 = 2 x 8,
- * 2 = 2 x 16).
+ * 2 = 2 x 16), "ks_streams" (2 = the relinearization / rotate-and-sum
+ * batches of lc_pairwise_sqdist and lc_pairwise_finish alternate between the
+ * caller's stream and a second stream of the library's, made on the first
+ * such call on that caller stream, forked after the triples and joined
+ * before SumDis, so that batches overlap; 1 = all on the caller's stream).
  * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

@@ -198,6 +198,11 @@ int lc_ctx_destroy(lc_ctx *x)
         for (auto &kv : c->ws)
             for (int i = 0; i < 8; i++)
                 if (kv.second.slot[i]) hipFree(kv.second.slot[i]);
+        for (auto &kv : c->aux) {
+            hipStreamDestroy(kv.second.stream);
+            hipEventDestroy(kv.second.fork);
+            hipEventDestroy(kv.second.join);
+        }
     }
     delete x;
     return LC_OK;
@@ -808,22 +813,63 @@ int lc_pair_triples_acc(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t
 // relinearize the triples whose (d0, d1) sit at `d01` (stride 2S, becoming
 // the distances in place) and whose d2 sit at `d2` (stride d2_stride), then
 // rotate-and-sum and SumDis.
+// The second stream of caller stream s (made on first use: not inside a
+// HIP graph capture).
+static Ctx::Aux *aux_for(Ctx *c, hipStream_t s)
+{
+    auto it = c->aux.find(s);
+    if (it != c->aux.end()) return &it->second;
+    Ctx::Aux a;
+    if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
+        hipGetLastError();
+        if (a.stream) hipStreamDestroy(a.stream);
+        if (a.fork) hipEventDestroy(a.fork);
+        c->err = "could not create the pipeline's second stream";
+        return nullptr;
+    }
+    return &(c->aux[s] = a);
+}
+
+// Relinearization and rotate-and-sum of the P triples, a key-switch batch of
+// ks_chunk pairs at a time.  Batches touch disjoint pairs and their own
+// stream's workspace, so with ks_streams = 2 they alternate between the
+// caller's stream and a second one and overlap on the device (the kernels of
+// one batch are half VALU-bound, half waiting on memory); the second stream
+// forks from the caller's after the triples and joins it before SumDis.
 static int pairwise_finish(lc_ctx *x, Ctx *c, const u64 *d01_base, u64 d01_stride, const u64 *d2, u64 d2_stride,
                            int n, const int *plan, int nblocks, uint64_t *dist, uint64_t *sumdis, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     const u64 S = (u64)c->nq * c->N;
     const u64 P = (u64)n * (n - 1) / 2;
+    const u64 chunk = std::max<u64>(1, std::min<u64>(P, (u64)c->tune.ks_chunk));
     KsGroup g{};
     g.keys[0] = c->rlk;
     g.n = 1;
-    g.base = d01_base;
     g.base_stride = d01_stride;
-    g.out = dist;
     g.out_stride = 2 * S;
+    Ctx::Aux *ax = nullptr;
+    if (c->tune.ks_streams > 1 && P > chunk) {
+        if (!(ax = aux_for(c, s))) return LC_EHIP;
+        LC_HIP(c, hipEventRecord(ax->fork, s));
+        LC_HIP(c, hipStreamWaitEvent(ax->stream, ax->fork, 0));
+    }
     int rc;
-    if ((rc = keyswitch_hoisted(c, d2, d2_stride, P, &g, 1, s))) return rc;
-    if ((rc = lc_rotate_sum(x, dist, P, plan, nblocks, stream))) return rc;
+    u64 k = 0;
+    for (u64 p0 = 0; p0 < P; p0 += chunk, k++) {
+        const u64 B = std::min(chunk, P - p0);
+        hipStream_t st = (ax && (k & 1)) ? ax->stream : s;
+        g.base = d01_base + p0 * d01_stride;
+        g.out = dist + p0 * 2 * S;
+        if ((rc = keyswitch_hoisted(c, d2 + p0 * d2_stride, d2_stride, B, &g, 1, st))) return rc;
+        if ((rc = lc_rotate_sum(x, dist + p0 * 2 * S, B, plan, nblocks, st))) return rc;
+    }
+    if (ax) {
+        LC_HIP(c, hipEventRecord(ax->join, ax->stream));
+        LC_HIP(c, hipStreamWaitEvent(s, ax->join, 0));
+    }
     if (sumdis) return launch_sumdis(c, dist, 2 * S, n, 2, sumdis, s);
     return LC_OK;
 }
@@ -908,7 +954,7 @@ static int ntt_groups(lc_ctx *x, const lc_poly_group *groups, int ngroups, void 
     for (int g = 0; g < ngroups; g++) {
         const lc_poly_group &G = groups[g];
         if (G.log_n < MIXED_LOG_MIN || G.log_n > std::min(MIXED_LOG_MAX, c->log_n))
-            return fail(c, LC_EUNSUP, "group ring degrees must lie in 2^12 .. min(2^16, N)");
+            return fail(c, LC_EUNSUP, "group ring degrees must lie in 2^12 .. min(2^17, N)");
         if (G.nlimb < 1 || G.limb0 < 0 || G.limb0 + G.nlimb > c->ne) return fail(c, LC_EINVAL, "limb range outside the basis");
         if (G.count && !G.data) return fail(c, LC_EINVAL, "null buffer");
         if (!G.count) continue;
@@ -984,6 +1030,7 @@ int lc_footprint(const lc_ctx *x, int n, int len, int k_chunk, int flags, size_t
     // (streamed form) the encryption staging of one chunk
     const u64 kc = std::min<u64>(P, (u64)c->tune.ks_chunk);
     u64 ws = kc * ks_words_per_ct(c) + kc * 2 * S;
+    if (c->tune.ks_streams > 1 && P > kc) ws *= 2;  // the second stream's batches
     if (k < (u64)len) ws += std::min<u64>((u64)n * k, std::max<u64>(1, (1ull << 31) / (3 * S * 8))) * 3 * S;
     else ws += P * S;
     if (round_bytes) *round_bytes = words * 8;
@@ -1035,6 +1082,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "mac_cycle_min") {
         if (value < 1) return fail(c, LC_EINVAL, "mac_cycle_min: >= 1");
         c->tune.mac_cycle_min = value;
+    } else if (k == "ks_streams") {
+        if (value != 1 && value != 2) return fail(c, LC_EINVAL, "ks_streams: 1/2");
+        c->tune.ks_streams = value;
     } else if (k == "ntt_sub_kb") {
         if (value < 0 || value > (1 << 22)) return fail(c, LC_EINVAL, "ntt_sub_kb: 0..4194304");
         c->tune.ntt_sub_kb = value;

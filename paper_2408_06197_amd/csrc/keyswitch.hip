@@ -605,7 +605,7 @@ int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const Ks
         u64 *v = acc + B * 2 * ne * N;
         const u64 *xb = x + b0 * x_stride;
         u64 words = (u64)nq * N;
-        const bool fused = c->tune.fuse_modup && c->log_n >= 10 && c->log_n <= 16 && x_stride % N == 0;
+        const bool fused = c->tune.fuse_modup && c->log_n >= 10 && c->log_n <= 17 && x_stride % N == 0;
         if (!fused) {
             hipLaunchKernelGGL(strided_copy_kernel, dim3(blocks_for(words * B)), dim3(KS_THREADS), 0, s, xb, x_stride,
                                xhat, words, words, B);

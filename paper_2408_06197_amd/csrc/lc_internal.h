@@ -129,9 +129,19 @@ struct Ctx {
         int mac_cycle_short = 1; // blocks whose tile cycles are at most 2 tiles long skip the walk
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
         int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
+        int ks_streams = 2;   // streams the batches of a pairwise finish alternate over (1 or 2)
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
     std::map<int, DegreeTables> degree_tabs;  // by log_n, below the context's degree
+    // a second stream per caller stream (created on first use, default
+    // priority), so that independent key-switch batches of one call overlap
+    // on the device, and the events that fork it from and join it back to
+    // the caller's stream
+    struct Aux {
+        hipStream_t stream = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+    };
+    std::map<hipStream_t, Aux> aux;
 };
 
 // error helpers (set ctx->err and return the code)
@@ -207,18 +217,18 @@ struct PolyBatch {
     u64 comb_add_stride = 0;
     u64 *comb_out = nullptr;
     u64 comb_out_stride = 0;
-    // two-pass transforms (2^10 <= N <= 2^16) only: the first pass reads
+    // two-pass transforms (2^10 <= N <= 2^17) only: the first pass reads
     // group g, limb l from in_base + (g in_gstride + l) N instead of base
     // (an out-of-place transform; in_base is not written)
     const u64 *in_base = nullptr;
     u64 in_gstride = 0;  // in polynomials
 };
-// Polynomials of mixed ring degree 2^MIXED_LOG_MIN .. 2^16 in one launch per
+// Polynomials of mixed ring degree 2^MIXED_LOG_MIN .. 2^17 in one launch per
 // pass: group g is npoly limb-polynomials of degree 2^log_n contiguous at
 // base, polynomial p using modulus limb0 + p % nlimb; tw / ninv hold each
 // degree's twiddles (inverse ones for inverse transforms) and N^-1, by
 // log_n - MIXED_LOG_MIN.  block0 is filled in by the launcher.
-constexpr int MIXED_LOG_MIN = 12, MIXED_LOG_MAX = 16, MAX_MIXED = 16;
+constexpr int MIXED_LOG_MIN = 12, MIXED_LOG_MAX = 17, MAX_MIXED = 16;
 struct MixedGroup {
     u64 *base;
     u64 npoly;

@@ -116,15 +116,18 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(DevParams dp, Pol
 
 // ---- register-radix pass kernel (N >= 2^10) ---------------------------------
 //
-// Same passes, faster execution: LOG_S in [5, 8] is a compile-time constant
+// Same passes, faster execution: LOG_S in [5, 9] is a compile-time constant
 // and each lane owns 16 elements of one sub-transform.  The tile is staged in
-// LDS with coalesced global accesses; the pass then runs as two register
-// rounds separated by one LDS exchange:
-//   top round:    lane t holds a = (h << (LOG_S-4)) | t, h = 0..15 -- the four
-//                 stages acting on the top four bits of a;
-//   bottom round: lane t holds a = (t << 4) | h -- the remaining LOG_S - 4
-//                 stages (fewer than four leave independent groups).
-// Forward passes run top then bottom, inverse passes bottom then top.
+// LDS with coalesced global accesses; the pass then runs as register rounds
+// separated by LDS exchanges.  Round r (forward order) does stages 4r ..
+// min(4r + 3, LOG_S - 1), which pair on bits of a inside [pos, pos + 4),
+// pos = max(0, LOG_S - 4 - 4r); lane t holds the 16 elements whose bits
+// [pos, pos + 4) are h = 0..15 and whose other bits are t:
+//   a = ((t >> pos) << (pos + 4)) | (h << pos) | (t & (2^pos - 1)).
+// LOG_S <= 8 takes two rounds (top: a = (h << (LOG_S-4)) | t; bottom:
+// a = (t << 4) | h, the remaining LOG_S - 4 stages), LOG_S = 9 three (the
+// last does stage 8 alone).  Forward passes run the rounds in order, inverse
+// passes in reverse.
 
 template <int LOG_S>
 __device__ __forceinline__ u32 lds_idx(u32 c, u32 a)
@@ -133,24 +136,37 @@ __device__ __forceinline__ u32 lds_idx(u32 c, u32 a)
     return c * (S + S / 16) + a + (a >> 4);  // one pad word per 16 breaks bank strides
 }
 
+template <int LOG_S>
+constexpr int round_count() { return (LOG_S + 3) / 4; }
+template <int LOG_S>
+constexpr int round_pos(int r) { return LOG_S - 4 - 4 * r > 0 ? LOG_S - 4 - 4 * r : 0; }
+
+// element index a of entry h of lane t in round r
+template <int LOG_S>
+__device__ __forceinline__ u32 round_elem(int r, u32 t, u32 h)
+{
+    const int pos = round_pos<LOG_S>(r);
+    return ((t >> pos) << (pos + 4)) | (h << pos) | (t & ((1u << pos) - 1));
+}
+
 template <int LOG_S, bool INVERSE>
-__device__ __forceinline__ void ntt_round(double (&x)[16], bool top, u32 t, u64 hi, int s0, const double *tw,
+__device__ __forceinline__ void ntt_round(double (&x)[16], int r, u32 t, u64 hi, int s0, const double *tw,
                                           double q, double qinv)
 {
-    constexpr int LB = LOG_S - 4;
+    const int pos = round_pos<LOG_S>(r);
     // local stages of this round, in execution order
-    int first = top ? 0 : 4, last = top ? 3 : LOG_S - 1;
+    const int first = 4 * r, last = 4 * r + 3 < LOG_S - 1 ? 4 * r + 3 : LOG_S - 1;
 #pragma unroll
     for (int it = 0; it < 4; it++) {
         int sl = INVERSE ? (last - it) : (first + it);
         if (sl < first || sl > last) continue;
         int bit = LOG_S - 1 - sl;                  // bit of a this stage pairs on
-        int hb = top ? (bit - LB) : bit;           // the same bit inside h
+        int hb = bit - pos;                        // the same bit inside h
         u64 base = (1ull << (s0 + sl)) + (hi << sl);
 #pragma unroll
         for (int h = 0; h < 16; h++) {
             if (h & (1 << hb)) continue;
-            u32 a1 = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
+            u32 a1 = round_elem<LOG_S>(r, t, (u32)h);
             double w = tw[base + (a1 >> (LOG_S - sl))];
             double X = x[h], Y = x[h | (1 << hb)];
             if (!INVERSE) {
@@ -195,7 +211,6 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
                                               const u64 *ntab, int s0, int cols, int final_, double *lds)
 {
     constexpr u32 S = 1u << LOG_S;
-    constexpr int LB = LOG_S - 4;
     constexpr u32 TPC = S / 16;  // lanes per sub-transform
     const double q = dp.mc[mi].qd, qinv = dp.mc[mi].qinv;
     const bool first_ = !final_;
@@ -300,20 +315,15 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
     const u32 c = tid / TPC, t = tid % TPC;
     const u64 hi = BLOCKS ? ((u64)tile * cols + c) : hi_col;
     double x[16];
+    constexpr int NR = round_count<LOG_S>();
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
-        bool top = INVERSE ? (r == 1) : (r == 0);
+    for (int k = 0; k < NR; k++) {
+        const int r = INVERSE ? NR - 1 - k : k;
 #pragma unroll
-        for (int h = 0; h < 16; h++) {
-            u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
-            x[h] = lds[lds_idx<LOG_S>(c, a)];
-        }
-        ntt_round<LOG_S, INVERSE>(x, top, t, hi, s0, tw, q, qinv);
+        for (int h = 0; h < 16; h++) x[h] = lds[lds_idx<LOG_S>(c, round_elem<LOG_S>(r, t, (u32)h))];
+        ntt_round<LOG_S, INVERSE>(x, r, t, hi, s0, tw, q, qinv);
 #pragma unroll
-        for (int h = 0; h < 16; h++) {
-            u32 a = top ? (((u32)h << LB) | t) : ((t << 4) | (u32)h);
-            lds[lds_idx<LOG_S>(c, a)] = x[h];
-        }
+        for (int h = 0; h < 16; h++) lds[lds_idx<LOG_S>(c, round_elem<LOG_S>(r, t, (u32)h))] = x[h];
         __syncthreads();
     }
     const double ni = (double)(pb.iscale ? pb.iscale[mi] : ntab[mi]);
@@ -407,11 +417,11 @@ struct FastPass {
     int s0, log_s, blocks, cols;
 };
 
-// Two passes for 2^10 <= N <= 2^16: columns of the top half of the stages,
+// Two passes for 2^10 <= N <= 2^17: columns of the top half of the stages,
 // then contiguous blocks.  At most 4096 elements per workgroup.
 static int plan_fast(int log_n, FastPass *p)
 {
-    if (log_n < 10 || log_n > 16) return 0;
+    if (log_n < 10 || log_n > 17) return 0;
     int k1 = log_n / 2, k2 = log_n - k1;  // k1 <= k2, both in [5, 8]
     u32 stride1 = 1u << k2;
     p[0] = {0, k1, 0, (int)std::min<u32>(4096u >> k1, stride1)};
@@ -427,13 +437,14 @@ static void launch_fast_one(int log_s, dim3 grid, dim3 block, size_t lds, hipStr
     case 5: hipLaunchKernelGGL((ntt_fast_kernel<5, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     case 6: hipLaunchKernelGGL((ntt_fast_kernel<6, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     case 7: hipLaunchKernelGGL((ntt_fast_kernel<7, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
-    default: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    case 8: hipLaunchKernelGGL((ntt_fast_kernel<8, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
+    default: hipLaunchKernelGGL((ntt_fast_kernel<9, INV, BLOCKS, MODE>), grid, block, lds, s, dp, b, s0, cols, final_); break;
     }
 }
 
 // ---- mixed ring degrees in one launch per pass ------------------------------
 //
-// For 2^12 <= N <= 2^16 both passes of the two-pass plan have 4096-element
+// For 2^12 <= N <= 2^17 both passes of the two-pass plan have 4096-element
 // tiles and 256-lane workgroups (columns: LOG_S = floor(log N / 2), 4096 /
 // 2^LOG_S sub-transforms per tile; blocks: LOG_S = ceil(log N / 2)), so one
 // launch can hold polynomials of several degrees: workgroup b finds its group
@@ -472,7 +483,8 @@ __global__ void __launch_bounds__(256) ntt_mixed_kernel(DevParams dp, MixedArgs 
     const int ls = BLOCKS ? G.log_n - G.log_n / 2 : G.log_n / 2;
     if (ls == 6) mixed_body<INVERSE, BLOCKS, 6>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
     else if (ls == 7) mixed_body<INVERSE, BLOCKS, 7>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
-    else mixed_body<INVERSE, BLOCKS, 8>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
+    else if (ls == 8) mixed_body<INVERSE, BLOCKS, 8>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
+    else mixed_body<INVERSE, BLOCKS, 9>(dp, pb, poly, mi, tile, N_, tw, ntab, final_, lds);
 }
 
 int launch_ntt_mixed(Ctx *c, const MixedArgs &ma0, bool inverse, hipStream_t s)
@@ -577,8 +589,8 @@ static int launch(Ctx *c, const PolyBatch &b, hipStream_t s, bool inverse)
         }
         return LC_OK;
     }
-    if (b.conv || b.comb_out || b.out_f64) return fail(c, LC_EINVAL, "fused key-switch transforms need 2^10 <= N <= 2^16");
-    if (b.in_base) return fail(c, LC_EINVAL, "an out-of-place transform needs 2^10 <= N <= 2^16");
+    if (b.conv || b.comb_out || b.out_f64) return fail(c, LC_EINVAL, "fused key-switch transforms need 2^10 <= N <= 2^17");
+    if (b.in_base) return fail(c, LC_EINVAL, "an out-of-place transform needs 2^10 <= N <= 2^17");
     PassArgs pass[2];
     int np = plan_passes(c->log_n, pass);
     for (int k = 0; k < np; k++) {

@@ -330,12 +330,13 @@ int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, con
 // workgroup on each CU.)
 //
 // Arithmetic is the FP64 Barrett form of modarith.h: differences x = a - b
-// lie in (-q, q), so |x y / q| < q < 2^50 and the quotient estimate is off by
-// less than 1, giving each product as an integer r with |r| < q.  The
-// accumulators (|acc| <= q/2 + 1 after a reduction) take PT_KB = 4 such
-// products before the next reduction (the cross term is accumulated once and
-// doubled at the end), so they stay below 4.5 q < 2^53 and every value is exact.  The
-// canonical residue is taken once at the end.
+// lie in (-q, q), so |x y / q| < q < 2^50; the quotient estimate rint(fl(fl(x
+// y) fl(1/q))) is off by at most 1/2 + 3 2^-53 |x y / q| < 7/8, giving each
+// product as an integer r with |r| < 7q/8.  The accumulators (|acc| <= q/2 +
+// 1 after a reduction) take two batches of PT_KB = 4 such products before the
+// next reduction (the cross term is accumulated once and doubled at the end),
+// so they stay below 7.5 q + 1 < 2^53 and every value is exact; the last
+// batch always reduces.  The canonical residue is taken once at the end.
 
 constexpr int PT_MAXN = 64;     // clients per call
 constexpr int PT_KB = 4;        // packed ciphertexts staged per barrier
@@ -357,7 +358,7 @@ __device__ __forceinline__ void pair_of_index(int p, int n, int &i, int &j)
 __host__ __device__ inline int pair_index(int n, int i, int j) { return i * (2 * n - i - 1) / 2 + (j - i - 1); }
 
 template <int T, int PPT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PPT <= 4 ? 6 : 4)))
 pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, int P, u64 *d01, u64 d01_stride,
                     u64 *d2, u64 d2_stride, int accumulate)
 {
@@ -467,6 +468,8 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
             // (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
+    };
+    auto reduce_all = [&]() {
 #pragma unroll
         for (int r = 0; r < PPT; r++) {
             acc[r][0] = reduce_d(acc[r][0], q, qinv);
@@ -485,6 +488,7 @@ pair_triples_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
         __syncthreads();
         if (k0 + PT_KB < len) issue(k0 + PT_KB, nb);
         compute(tb);
+        if (cur == 1 || k0 + PT_KB >= len) reduce_all();  // every second batch, and the last
     }
     const u64 o = (u64)l * N + (u64)blockIdx.x * T + lane;
 #pragma unroll

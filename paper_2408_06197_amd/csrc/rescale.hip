@@ -63,7 +63,7 @@ int launch_rescale(Ctx *c, const u64 *ct, u64 count, int ncomp, int nlimb, u64 *
     const u64 chunk = std::min<u64>(groups, std::max<u64>(1, (1ull << 30) / per_group));
     u64 *ws = ws_get(c, WS_RESCALE, chunk * per_group, s);
     if (!ws) return LC_ENOMEM;
-    const bool two_pass = c->log_n >= 10 && c->log_n <= 16;
+    const bool two_pass = c->log_n >= 10 && c->log_n <= 17;
     int rc;
     for (u64 g0 = 0; g0 < groups; g0 += chunk) {
         const u64 G = std::min(chunk, groups - g0);

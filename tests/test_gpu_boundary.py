@@ -6,7 +6,7 @@ degrees and per-client SumDis, against the CPU oracle on the same inputs:
     relinearizes, rotates and runs the whole distance pipeline bit for bit
     as the oracle does with those keys;
   * lc_ntt_fwd_groups / lc_ntt_inv_groups: polynomials of ring degrees
-    2^12 .. 2^16 in one launch per pass equal the oracle's transform of each
+    2^12 .. 2^17 in one launch per pass equal the oracle's transform of each
     degree, and the inverse restores them;
   * lc_sumdis_lazy: per-client SumDis with one relinearization per client
     equals the oracle's composition of pair triples, sums, relinearization
@@ -159,6 +159,27 @@ def test_ntt_groups_bitexact(torch, L, oracle_mod):
     small.ntt_fwd(g1, nlimb=6)
     ctx.ntt_fwd_groups([(g2, 14, 6, 0)])
     assert torch.equal(g1, g2)
+
+
+def test_ntt_groups_degree_2_17(torch, L, oracle_mod):
+    """Degrees 2^17 (its second pass has 512-point sub-transforms in three
+    register rounds) and 2^12 in one call on a degree-2^17 context."""
+    O = oracle_mod
+    qb, pb = (50,) * 3, (50,)
+    ctx = L.Context(17, qb, pb, device=0)
+    host = [synth.uniform_residues(71, ctx.moduli[:3], (2, 1 << 17)),
+            synth.uniform_residues(72, ctx.moduli[1:3], (3, 1 << 12))]
+    dev = [up(torch, x) for x in host]
+    groups = [(dev[0], 17, 3, 0), (dev[1], 12, 2, 1)]
+    ctx.ntt_fwd_groups(groups)
+    o17, o12 = O.Oracle(17, qb, pb), O.Oracle(12, qb, pb, log_m=18)
+    assert o17.primes == ctx.moduli and o12.primes == ctx.moduli
+    for c in range(2):
+        assert np.array_equal(down(dev[0])[c], o17.poly_ntt(host[0][c]))
+    for c in range(3):
+        assert np.array_equal(down(dev[1])[c], o12.poly_ntt(host[1][c], 1))
+    ctx.ntt_inv_groups(groups)
+    assert np.array_equal(down(dev[0]), host[0]) and np.array_equal(down(dev[1]), host[1])
 
 
 def test_ntt_groups_rejects(torch, L):

@@ -493,9 +493,10 @@ def test_ntt_sub_batches_bitexact(torch, L, oracle_mod, log_n):
 
 
 def test_ks_tuning_bitexact(torch, L, oracle_mod):
-    """The pipeline's key switches with one- and three-ciphertext chunks and
-    tiny NTT sub-batches (whole digit groups with own-digit limbs skipped)
-    give the oracle's bits."""
+    """The pipeline's key switches with one- and three-ciphertext chunks,
+    alternating over two streams or all on one, and tiny NTT sub-batches
+    (whole digit groups with own-digit limbs skipped) give the oracle's
+    bits."""
     O = oracle_mod
     w = KS_W
     ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
@@ -503,13 +504,15 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
     ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
     upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
     res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps])
-    for chunk, sub, mac, fuse in ((1, 64, 8, 1), (3, 64, 16, 0), (64, 0, 16, 1), (64, 0, 8, 0), (3, 64, 8, 1)):
+    for chunk, sub, mac, fuse, streams in ((1, 64, 8, 1, 2), (3, 64, 16, 0, 2), (64, 0, 16, 1, 2), (64, 0, 8, 0, 2),
+                                           (3, 64, 8, 1, 2), (3, 0, 16, 1, 1), (1, 0, 8, 1, 1)):
         ctx.set_tuning("ks_chunk", chunk)
         ctx.set_tuning("ntt_sub_kb", sub)
         ctx.set_tuning("mac_cts", mac)
         ctx.set_tuning("fuse_modup", fuse)
+        ctx.set_tuning("ks_streams", streams)
         dist = ctx.pairwise_sqdist(up(torch, cts), plan=list(w.rot_plan))
-        assert np.array_equal(down(dist), res["dist"]), (chunk, sub, mac, fuse)
+        assert np.array_equal(down(dist), res["dist"]), (chunk, sub, mac, fuse, streams)
 
 
 def test_set_tuning_rejects_bad_values(L):
@@ -517,7 +520,7 @@ def test_set_tuning_rejects_bad_values(L):
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("pair_mfma", 3), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
                         ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
                         ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("mac_cycle_short", 2), ("mac_short_cts", 4),
-                        ("nope", 1)):
+                        ("ks_streams", 3), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
