@@ -371,7 +371,11 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * batches of lc_pairwise_sqdist and lc_pairwise_finish alternate between the
  * caller's stream and a second stream of the library's, made on the first
  * such call on that caller stream, forked after the triples and joined
- * before SumDis, so that batches overlap; 1 = all on the caller's stream).
+ * before SumDis, so that batches overlap; 1 = all on the caller's stream),
+ * "mac_xcd" (1 = the walking and short-cycle inner-product workgroups that
+ * read the same key tiles for different ciphertexts are dispatched to one
+ * XCD back to back, so the keys come from that XCD's L2 after the first
+ * read; 0 = plain grid order).
  * LC_EINVAL for unknown names/values. */
 int lc_set_tuning(lc_ctx *ctx, const char *name, int value);
 

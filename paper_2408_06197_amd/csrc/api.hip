@@ -1085,6 +1085,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "ks_streams") {
         if (value != 1 && value != 2) return fail(c, LC_EINVAL, "ks_streams: 1/2");
         c->tune.ks_streams = value;
+    } else if (k == "mac_xcd") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_xcd: 0/1");
+        c->tune.mac_xcd = value;
     } else if (k == "ntt_sub_kb") {
         if (value < 0 || value > (1 << 22)) return fail(c, LC_EINVAL, "ntt_sub_kb: 0..4194304");
         c->tune.ntt_sub_kb = value;

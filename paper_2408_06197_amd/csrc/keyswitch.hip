@@ -13,6 +13,8 @@
 //   4. ModDown: (acc_Q - BConv_{P->Q}(iNTT(acc_P)))^ * P^-1 mod q_l;
 //   5. out0 = base0 + sum_t phi_t(c0src) + ModDown(acc_0), out1 = base1 +
 //      ModDown(acc_1).
+#include <numeric>
+
 #include "lc_internal.h"
 
 namespace lc {
@@ -175,19 +177,42 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
 // same source tiles, so it is staged with the digits and added to the Q
 // limbs of accumulator 0 times P mod q (exact after ModDown, which divides
 // by P), and the combine kernel skips its per-key gathers of c0.
+// Workgroups are dealt to the 8 XCDs round-robin in dispatch order (x
+// fastest).  With remap set (the launch pads gx so that gx * gy is a
+// multiple of 8; workgroups with x past the real count return at once), the
+// gz workgroups that share (x, y) -- the same key tiles, for different
+// ciphertexts -- are made consecutive on one XCD, so all but the first find
+// the keys in its L2.
+__device__ __forceinline__ void mac_block_ids(int remap, u32 &bx, u32 &by, u32 &bz)
+{
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+    if (!remap) return;
+    const u32 gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const u32 lin = bx + gx * (by + gy * bz);
+    const u32 j = lin >> 3, xy = (j / gz) * 8 + (lin & 7);
+    bz = j % gz;
+    bx = xy % gx;
+    by = xy / gx;
+}
+
 template <int R, int D, int CB, bool FOLD>
 __global__ void __launch_bounds__(KS_CYC_TILE * CB, CB == 8 ? 3 : 1)
 mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
-                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count)
+                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count, int remap, u32 nx)
 {
     constexpr int TT = KS_CYC_TILE;
     constexpr int XD = FOLD ? D + 1 : D;     // staged rows per ciphertext: D digits (and c0)
     __shared__ double xt[CB * XD * TT];      // [CB][XD][TT]: source tile c_p
     __shared__ double kt[R * 2 * D * TT];    // [R][2 D][TT]: keys of the outputs c_{p-1} .. c_{p-R}
     const int u = threadIdx.x, bl = threadIdx.y;
-    const CycleSeg sg = segs[blockIdx.x];
-    const int l = blockIdx.y;
-    const u64 b = (u64)blockIdx.z * CB + bl;
+    u32 bx, by, bz;
+    mac_block_ids(remap, bx, by, bz);
+    if (bx >= nx) return;  // launch padding
+    const CycleSeg sg = segs[bx];
+    const int l = (int)by;
+    const u64 b = (u64)bz * CB + bl;
     const bool live = b < count;
     const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
@@ -296,24 +321,27 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
 template <int R, int D, int CB, bool FOLD, int LM>
 __global__ void __launch_bounds__(KS_CYC_TILE * CB)
 mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
-                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count)
+                 KeySet ks, const CycleSeg *segs, const u32 *walk, u64 *acc, u64 count, int remap, u32 nx)
 {
     constexpr int TT = KS_CYC_TILE;
     constexpr int XD = FOLD ? D + 1 : D;
     __shared__ double xt[LM * CB * XD * TT];  // [LM][CB][XD][TT]: the cycle's source tiles
     __shared__ double kt[R * 2 * D * TT];     // [R][2 D][TT]: keys of one output tile
     const int u = threadIdx.x, bl = threadIdx.y;
+    u32 bx, by, bz;
+    mac_block_ids(remap, bx, by, bz);
+    if (bx >= nx) return;  // launch padding
     // With one-tile cycles the walk is the identity (tile i is segment i), so
     // the tables are not read.
-    int L = 1, base = (int)blockIdx.x;
+    int L = 1, base = (int)bx;
     if (LM > 1) {
-        const CycleSeg sg = segs[blockIdx.x];
+        const CycleSeg sg = segs[bx];
         L = sg.len;  // <= LM (checked when the kernel is chosen)
         base = sg.base;
     }
-    auto tile = [&](int i) -> u64 { return LM == 1 ? (u64)blockIdx.x : (u64)walk[base + i]; };
-    const int l = blockIdx.y;
-    const u64 b = (u64)blockIdx.z * CB + bl;
+    auto tile = [&](int i) -> u64 { return LM == 1 ? (u64)bx : (u64)walk[base + i]; };
+    const int l = (int)by;
+    const u64 b = (u64)bz * CB + bl;
     const bool live = b < count;
     const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
@@ -410,13 +438,13 @@ mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
 template <int R, int CB, bool FOLD>
 static void launch_mac_cycle_cb(int short_lm, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x, u64 x_stride,
                                 const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
-                                const CycleTable *cyc, u64 *acc, u64 count)
+                                const CycleTable *cyc, u64 *acc, u64 count, int remap, u32 nx)
 {
     dim3 block(KS_CYC_TILE, CB);
     if (short_lm == 1 || short_lm == 2) {
 #define LC_SHORT(DD, LMV)                                                                                        \
     hipLaunchKernelGGL((mac_short_kernel<R, DD, CB, FOLD, LMV>), grid, block, 0, s, dp, x, x_stride, raised, c0, \
-                       c0_stride, ks, cyc->segs, cyc->walk, acc, count)
+                       c0_stride, ks, cyc->segs, cyc->walk, acc, count, remap, nx)
         if (short_lm == 1) {
             if (dnum == 3) LC_SHORT(3, 1); else if (dnum == 4) LC_SHORT(4, 1); else LC_SHORT(6, 1);
         } else {
@@ -427,21 +455,21 @@ static void launch_mac_cycle_cb(int short_lm, int dnum, dim3 grid, hipStream_t s
     }
     switch (dnum) {
     case 3: hipLaunchKernelGGL((mac_cycle_kernel<R, 3, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
-                               c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+                               c0_stride, ks, cyc->segs, cyc->walk, acc, count, remap, nx); break;
     case 4: hipLaunchKernelGGL((mac_cycle_kernel<R, 4, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
-                               c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+                               c0_stride, ks, cyc->segs, cyc->walk, acc, count, remap, nx); break;
     default: hipLaunchKernelGGL((mac_cycle_kernel<R, 6, CB, FOLD>), grid, block, 0, s, dp, x, x_stride, raised, c0,
-                                c0_stride, ks, cyc->segs, cyc->walk, acc, count); break;
+                                c0_stride, ks, cyc->segs, cyc->walk, acc, count, remap, nx); break;
     }
 }
 
 template <int R, bool FOLD>
 static void launch_mac_cycle_r(int short_lm, int cb, int dnum, dim3 grid, hipStream_t s, const DevParams &dp, const u64 *x,
                                u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride, const KeySet &ks,
-                               const CycleTable *cyc, u64 *acc, u64 count)
+                               const CycleTable *cyc, u64 *acc, u64 count, int remap, u32 nx)
 {
-    if (cb == 16) launch_mac_cycle_cb<R, 16, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-    else launch_mac_cycle_cb<R, 8, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+    if (cb == 16) launch_mac_cycle_cb<R, 16, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
+    else launch_mac_cycle_cb<R, 8, FOLD>(short_lm, dnum, grid, s, dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
 }
 
 // ciphertexts per workgroup: 8 or 16 (tuning "mac_cycle_cts" for walks,
@@ -454,12 +482,18 @@ static void launch_mac_cycle(const Ctx *c, int R, u64 nseg, hipStream_t s, const
     const int short_lm = c->tune.mac_cycle_short && cyc->max_len <= 2 ? cyc->max_len : 0;
     const int cb = (short_lm ? c->tune.mac_short_cts : c->tune.mac_cycle_cts) == 16 ? 16 : 8;
     dim3 grid((u32)nseg, (u32)c->ne, (u32)((count + cb - 1) / cb));
+    const u32 nx = (u32)nseg;
+    const int remap = c->tune.mac_xcd && grid.z > 1;
+    if (remap) {  // pad x so that x * y is a multiple of 8
+        const u32 m = 8u / std::gcd(grid.y, 8u);
+        grid.x = (grid.x + m - 1) / m * m;
+    }
     if (R == 3) {
-        if (c0) launch_mac_cycle_r<3, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-        else launch_mac_cycle_r<3, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        if (c0) launch_mac_cycle_r<3, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
+        else launch_mac_cycle_r<3, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
     } else {
-        if (c0) launch_mac_cycle_r<7, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
-        else launch_mac_cycle_r<7, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count);
+        if (c0) launch_mac_cycle_r<7, true>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
+        else launch_mac_cycle_r<7, false>(short_lm, cb, c->dnum, grid, s, c->dp, x, x_stride, raised, c0, c0_stride, ks, cyc, acc, count, remap, nx);
     }
 }
 

@@ -130,6 +130,7 @@ struct Ctx {
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
         int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
         int ks_streams = 2;   // streams the batches of a pairwise finish alternate over (1 or 2)
+        int mac_xcd = 1;      // cycle-walk / short-cycle workgroups sharing key tiles run on one XCD
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
     std::map<int, DegreeTables> degree_tabs;  // by log_n, below the context's degree

@@ -321,18 +321,22 @@ def test_rotate_sum_cycle_walk_bitexact(torch, L, oracle_mod, prm, plan):
     cts = ora.encrypt(5, 0, m, keys["pk"])
     want = [ora.rotate_sum(cts[c], plan, [keys["rot"][k] for k in steps]) for c in (0, 7, 10)]
     ctx.set_tuning("mac_cycle_min", 1)  # every block walks, even one-tile cycles
-    for cyc, cts_per_wg, fold, one in ((1, 8, 1, 1), (1, 16, 1, 1), (1, 8, 0, 1), (1, 16, 0, 0), (1, 8, 1, 0),
-                                       (0, 8, 1, 1)):
+    # xcd: the workgroups of one key tile grouped on one XCD (two groups of
+    # ciphertexts at 8 per workgroup, segment count padded)
+    for cyc, cts_per_wg, fold, one, xcd in ((1, 8, 1, 1, 0), (1, 16, 1, 1, 0), (1, 8, 0, 1, 0), (1, 16, 0, 0, 0),
+                                            (1, 8, 1, 0, 0), (0, 8, 1, 1, 0), (1, 8, 1, 1, 1), (1, 8, 0, 0, 1),
+                                            (1, 8, 1, 0, 1)):
         ctx.set_tuning("mac_cycle", cyc)
         ctx.set_tuning("mac_cycle_cts", cts_per_wg)
         ctx.set_tuning("mac_short_cts", cts_per_wg)
         ctx.set_tuning("mac_cycle_c0", fold)
         ctx.set_tuning("mac_cycle_short", one)  # 1: cycles of <= 2 tiles take the no-walk kernel
+        ctx.set_tuning("mac_xcd", xcd)
         g = up(torch, cts)
         ctx.rotate_sum(g, plan)
         got = down(g)
         for w, c in zip(want, (0, 7, 10)):
-            assert np.array_equal(got[c], w), (cyc, cts_per_wg, fold, one, c)
+            assert np.array_equal(got[c], w), (cyc, cts_per_wg, fold, one, xcd, c)
 
 
 def test_rotate_sum_cycle_walk_full_size(torch, L, oracle_mod):
@@ -494,9 +498,10 @@ def test_ntt_sub_batches_bitexact(torch, L, oracle_mod, log_n):
 
 def test_ks_tuning_bitexact(torch, L, oracle_mod):
     """The pipeline's key switches with one- and three-ciphertext chunks,
-    alternating over two streams or all on one, and tiny NTT sub-batches
-    (whole digit groups with own-digit limbs skipped) give the oracle's
-    bits."""
+    alternating over two streams or all on one, tiny NTT sub-batches (whole
+    digit groups with own-digit limbs skipped), the base conversions fused
+    into the transforms or not, and XCD-grouped inner-product workgroups give
+    the oracle's bits."""
     O = oracle_mod
     w = KS_W
     ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
@@ -504,15 +509,17 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
     ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
     upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
     res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps])
-    for chunk, sub, mac, fuse, streams in ((1, 64, 8, 1, 2), (3, 64, 16, 0, 2), (64, 0, 16, 1, 2), (64, 0, 8, 0, 2),
-                                           (3, 64, 8, 1, 2), (3, 0, 16, 1, 1), (1, 0, 8, 1, 1)):
+    for chunk, sub, mac, fuse, streams, xcd in ((1, 64, 8, 1, 2, 0), (3, 64, 16, 0, 2, 1), (64, 0, 16, 1, 2, 1),
+                                                (64, 0, 8, 0, 2, 0), (3, 64, 8, 1, 2, 0), (3, 0, 16, 1, 1, 1),
+                                                (1, 0, 8, 1, 1, 0)):
         ctx.set_tuning("ks_chunk", chunk)
         ctx.set_tuning("ntt_sub_kb", sub)
         ctx.set_tuning("mac_cts", mac)
         ctx.set_tuning("fuse_modup", fuse)
         ctx.set_tuning("ks_streams", streams)
+        ctx.set_tuning("mac_xcd", xcd)
         dist = ctx.pairwise_sqdist(up(torch, cts), plan=list(w.rot_plan))
-        assert np.array_equal(down(dist), res["dist"]), (chunk, sub, mac, fuse, streams)
+        assert np.array_equal(down(dist), res["dist"]), (chunk, sub, mac, fuse, streams, xcd)
 
 
 def test_set_tuning_rejects_bad_values(L):
@@ -520,7 +527,7 @@ def test_set_tuning_rejects_bad_values(L):
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("pair_mfma", 3), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
                         ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
                         ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("mac_cycle_short", 2), ("mac_short_cts", 4),
-                        ("ks_streams", 3), ("nope", 1)):
+                        ("ks_streams", 3), ("mac_xcd", 2), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
