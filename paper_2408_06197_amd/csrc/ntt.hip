@@ -129,11 +129,38 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(DevParams dp, Pol
 // last does stage 8 alone).  Forward passes run the rounds in order, inverse
 // passes in reverse.
 
-template <int LOG_S>
+// LDS layout of a tile: sub-transform c holds its S elements with one pad
+// word per 16.  A 16-lane group of a wave accesses LDS in one go over 32
+// banks of 4 bytes.  The rounds read and write 16 consecutive pad-free runs
+// of one or two sub-transforms, which never conflict.  The coalesced staging
+// of a column pass (and its read-out) instead touches the same element a of
+// 8 to 16 sub-transforms at once, which with a stride of S + S / 16 words
+// (a multiple of 16 doubles for S >= 256) all fall in the same two banks.
+// So column tiles get a sub-transform stride one (S = 256) or two (S = 512)
+// doubles longer, and below 256 points, where one 16-lane group of a round
+// spans several sub-transforms and the stride has to stay, the element
+// index is XORed with bits of c (a permutation inside each run of 16, so
+// the pad words stay put).  Block tiles keep the plain layout: their staging
+// is already conflict-free.
+template <int LOG_S, bool BLOCKS>
+constexpr u32 lds_stride()
+{
+    return (1u << LOG_S) + (1u << LOG_S) / 16 + (BLOCKS ? 0u : LOG_S == 8 ? 1u : LOG_S == 9 ? 2u : 0u);
+}
+
+template <int LOG_S, bool BLOCKS>
 __device__ __forceinline__ u32 lds_idx(u32 c, u32 a)
 {
-    constexpr u32 S = 1u << LOG_S;
-    return c * (S + S / 16) + a + (a >> 4);  // one pad word per 16 breaks bank strides
+    if (!BLOCKS && LOG_S < 8) a ^= (c >> (8 - LOG_S)) & 15u;
+    return c * lds_stride<LOG_S, BLOCKS>() + a + (a >> 4);
+}
+
+// LDS bytes of a tile (4096 elements), host side
+static size_t fast_lds_bytes(int log_s, bool blocks)
+{
+    const size_t S = (size_t)1 << log_s;
+    const size_t extra = blocks ? 0 : log_s == 8 ? 1 : log_s == 9 ? 2 : 0;
+    return (4096 / S) * (S + S / 16 + extra) * sizeof(double);
 }
 
 template <int LOG_S>
@@ -307,7 +334,7 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
         if (BLOCKS) { c = e >> LOG_S; a = e & (S - 1); }
         else { a = e / (u32)cols; c = e % (u32)cols; }
         // BLOCKS: (c, a), (c, a+1); columns: (c, a), (c+1, a)
-        u32 i0 = lds_idx<LOG_S>(c, a), i1 = BLOCKS ? lds_idx<LOG_S>(c, a + 1) : lds_idx<LOG_S>(c + 1, a);
+        u32 i0 = lds_idx<LOG_S, BLOCKS>(c, a), i1 = BLOCKS ? lds_idx<LOG_S, BLOCKS>(c, a + 1) : lds_idx<LOG_S, BLOCKS>(c + 1, a);
         lds[i0] = v[2 * i];
         lds[i1] = v[2 * i + 1];
     }
@@ -320,10 +347,10 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
     for (int k = 0; k < NR; k++) {
         const int r = INVERSE ? NR - 1 - k : k;
 #pragma unroll
-        for (int h = 0; h < 16; h++) x[h] = lds[lds_idx<LOG_S>(c, round_elem<LOG_S>(r, t, (u32)h))];
+        for (int h = 0; h < 16; h++) x[h] = lds[lds_idx<LOG_S, BLOCKS>(c, round_elem<LOG_S>(r, t, (u32)h))];
         ntt_round<LOG_S, INVERSE>(x, r, t, hi, s0, tw, q, qinv);
 #pragma unroll
-        for (int h = 0; h < 16; h++) lds[lds_idx<LOG_S>(c, round_elem<LOG_S>(r, t, (u32)h))] = x[h];
+        for (int h = 0; h < 16; h++) lds[lds_idx<LOG_S, BLOCKS>(c, round_elem<LOG_S>(r, t, (u32)h))] = x[h];
         __syncthreads();
     }
     const double ni = (double)(pb.iscale ? pb.iscale[mi] : ntab[mi]);
@@ -349,8 +376,8 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
             const u32 e = 2 * (tid + (u32)i * nthreads);
             const u32 cc = e >> LOG_S, a = e & (S - 1);
             const u64 g = ((u64)tile * cols + cc) * S + a;
-            double r0 = mulmod_d(u64_to_d(a2[i].x) - lds[lds_idx<LOG_S>(cc, a)], pinv, q, qinv);
-            double r1 = mulmod_d(u64_to_d(a2[i].y) - lds[lds_idx<LOG_S>(cc, a + 1)], pinv, q, qinv);
+            double r0 = mulmod_d(u64_to_d(a2[i].x) - lds[lds_idx<LOG_S, BLOCKS>(cc, a)], pinv, q, qinv);
+            double r1 = mulmod_d(u64_to_d(a2[i].y) - lds[lds_idx<LOG_S, BLOCKS>(cc, a + 1)], pinv, q, qinv);
             if (addp) {
                 r0 += u64_to_d(b2[i].x);
                 r1 += u64_to_d(b2[i].y);
@@ -369,8 +396,8 @@ __device__ __forceinline__ void ntt_fast_body(const DevParams &dp, const PolyBat
         u64 g;
         if (BLOCKS) { cc = e >> LOG_S; a = e & (S - 1); g = ((u64)tile * cols + cc) * S + a; }
         else { a = e / (u32)cols; cc = e % (u32)cols; g = (hi_col * S + a) * stride + lo0 + cc; }
-        double d0 = lds[lds_idx<LOG_S>(cc, a)];
-        double d1 = BLOCKS ? lds[lds_idx<LOG_S>(cc, a + 1)] : lds[lds_idx<LOG_S>(cc + 1, a)];
+        double d0 = lds[lds_idx<LOG_S, BLOCKS>(cc, a)];
+        double d1 = BLOCKS ? lds[lds_idx<LOG_S, BLOCKS>(cc, a + 1)] : lds[lds_idx<LOG_S, BLOCKS>(cc + 1, a)];
         ulonglong2 o;
         if (final_) {
             if (INVERSE) {
@@ -497,7 +524,7 @@ int launch_ntt_mixed(Ctx *c, const MixedArgs &ma0, bool inverse, hipStream_t s)
     }
     if (blocks == 0) return LC_OK;
     if (blocks > 0x7fffffffull) return fail(c, LC_EINVAL, "too many polynomials in one NTT launch");
-    const size_t lds = (size_t)4096 * 17 / 16 * sizeof(double);
+    const size_t lds = fast_lds_bytes(8, false);  // the largest tile layout of the degrees 2^12 .. 2^17
     const dim3 grid((u32)blocks), block(256);
     if (!inverse) {
         hipLaunchKernelGGL((ntt_mixed_kernel<false, false>), grid, block, lds, s, c->dp, ma, 0);
@@ -535,7 +562,7 @@ static int launch_fast(Ctx *c, const PolyBatch &b, const FastPass *fp, hipStream
         u32 S = 1u << P.log_s;
         u32 tiles = (u32)(c->N >> P.log_s) / (u32)P.cols;
         dim3 grid((u32)npoly, tiles), block((u32)P.cols * (S / 16));
-        size_t lds = (size_t)P.cols * (S + S / 16) * sizeof(u64);
+        size_t lds = fast_lds_bytes(P.log_s, P.blocks);
         if (inverse) {
             if (P.blocks) launch_fast_one<true, true>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
             else launch_fast_one<true, false>(P.log_s, grid, block, lds, s, c->dp, b, P.s0, P.cols, final_);
