@@ -45,9 +45,9 @@ A2_SECTION = ("ops.hip", "// ---- fused subtract / square / lazy accumulate over
 # paper_2408_06197_amd.profile_cases ntt`, per-launch averages of the forward
 # passes; see profiles/ntt_fwd_n65536_l24_64cts_pmc.txt.  Empty until taken.
 NTT_SECTION = ("ntt.hip", "// ---- register-radix pass kernel", "struct FastPass {")
-NTT_PMC = {"fetch_bytes_per_launch": 2.0 * (393370 + 399435) / 2 * 1024, "write_bytes_per_launch": 786432 * 1024,
+NTT_PMC = {"fetch_bytes_per_launch": 2.0 * (393379 + 399428) / 2 * 1024, "write_bytes_per_launch": 786432 * 1024,
            "limb_polys": 1536,
-           "source_sha256": "a86d965bd578d5e3a3381f915880795e01d2f3d1237a77cc9cf6ee14348e5f94"}
+           "source_sha256": "94e0ef1e433c0177aac1b0d213d016d4572cdb4b1810e0552cc6d4398501ffbf"}
 
 
 def _source_sha256(fname, start, stop):
