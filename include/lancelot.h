@@ -360,7 +360,9 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * "mac_cycle_min" (>= 1: shortest tile cycle for which the walk is used),
  * "mac_cycle_cts" (8/16 ciphertexts per walking workgroup), "mac_short_cts"
  * (8/16 ciphertexts per short-cycle workgroup), "mac_cycle_c0"
- * (1 = the walk also adds the block's permuted c0 terms; 0 = the combine does),
+ * (1 = the inner product, walk or per-key gather, also adds the group's
+ * permuted c0 terms, so that ModDown's last transform pass does the whole
+ * combine; 0 = a combine kernel adds them),
  * "mac_cycle_short" (1 = blocks whose tile cycles are at most 2 tiles long,
  * such as rotations that keep every tile in place, stage each cycle once
  * instead of walking it),

@@ -98,9 +98,14 @@ __device__ __forceinline__ void stage_key_ptrs(const KeySet &ks, const u64 **kp,
 // tuning choice).  Products use the FP64 Barrett form (|x key| reduced to at
 // most 0.8125 q); the two accumulators per ciphertext are reduced after every
 // 8 products, so they stay below 7 q.
-template <int MAC_B>
+// With FOLD, c0 is given and the Q limbs of accumulator 0 also take
+// sum_t phi_t(c0) times P mod q (one more product per key, counted like the
+// others): ModDown divides it by P exactly, so the output gets the permuted
+// c0 terms without a combine kernel, as in the cycle walk.
+template <int MAC_B, bool FOLD>
 __global__ void __launch_bounds__(KS_THREADS)
-mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet ks, u64 *acc, u64 count)
+mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride, KeySet ks,
+           u64 *acc, u64 count)
 {
     u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;  // over ne * N
     u64 b0 = (u64)blockIdx.y * MAC_B;
@@ -137,6 +142,23 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, KeySet k
                 a0[b] += mulmod_d(xv, k0, q, qinv);
                 a1[b] += mulmod_d(xv, k1, q, qinv);
             }
+            if (++since == 8) {
+                since = 0;
+#pragma unroll
+                for (int b = 0; b < MAC_B; b++) {
+                    a0[b] = reduce_d(a0[b], q, qinv);
+                    a1[b] = reduce_d(a1[b], q, qinv);
+                }
+            }
+        }
+        if (FOLD && own_limb) {
+            const double pq = u64_to_d(dp.pmod[l]);
+            const u64 *cb = c0 + b0 * c0_stride + (u64)l * dp.N + src;
+            u64 v[MAC_B];
+#pragma unroll
+            for (int b = 0; b < MAC_B; b++) v[b] = cb[(u64)min(b, nb - 1) * c0_stride];
+#pragma unroll
+            for (int b = 0; b < MAC_B; b++) a0[b] += mulmod_d(u64_to_d(v[b]), pq, q, qinv);
             if (++since == 8) {
                 since = 0;
 #pragma unroll
@@ -684,25 +706,35 @@ int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const Ks
                              (dnum == 3 || dnum == 4 || dnum == 6) &&
                              (G.cyc->min_len >= c->tune.mac_cycle_min ||
                               (G.cyc->max_len <= 2 && c->tune.mac_cycle_short));
-            // the walk folds sum_t phi_t(c0) into the accumulator (then the
-            // combine kernel skips it)
-            const u64 *c0_fold = cyc && c->tune.mac_cycle_c0 && G.c0src ? G.c0src + b0 * G.c0_stride : nullptr;
+            // the inner product folds sum_t phi_t(c0) into the accumulator
+            // (then ModDown's last pass does the whole combine)
+            const u64 *c0_fold = c->tune.mac_cycle_c0 && G.c0src ? G.c0src + b0 * G.c0_stride : nullptr;
             if (cyc) {
                 launch_mac_cycle(c, G.n, (u64)G.cyc->nseg, s, xb, x_stride, raised, c0_fold, G.c0_stride, ks, G.cyc,
                                  acc, B);
-            } else if (c->tune.mac_cts == 16)
-                hipLaunchKernelGGL((mac_kernel<16>), dim3(blocks_for((u64)ne * N), (u32)((B + 15) / 16)),
-                                   dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
-            else
-                hipLaunchKernelGGL((mac_kernel<8>), dim3(blocks_for((u64)ne * N), (u32)((B + 7) / 8)),
-                                   dim3(KS_THREADS), 0, s, c->dp, xb, x_stride, raised, ks, acc, B);
+            } else {
+                const dim3 grid(blocks_for((u64)ne * N), (u32)((B + c->tune.mac_cts - 1) / c->tune.mac_cts));
+                if (c->tune.mac_cts == 16 && c0_fold)
+                    hipLaunchKernelGGL((mac_kernel<16, true>), grid, dim3(KS_THREADS), 0, s, c->dp, xb, x_stride,
+                                       raised, c0_fold, G.c0_stride, ks, acc, B);
+                else if (c->tune.mac_cts == 16)
+                    hipLaunchKernelGGL((mac_kernel<16, false>), grid, dim3(KS_THREADS), 0, s, c->dp, xb, x_stride,
+                                       raised, nullptr, 0, ks, acc, B);
+                else if (c0_fold)
+                    hipLaunchKernelGGL((mac_kernel<8, true>), grid, dim3(KS_THREADS), 0, s, c->dp, xb, x_stride,
+                                       raised, c0_fold, G.c0_stride, ks, acc, B);
+                else
+                    hipLaunchKernelGGL((mac_kernel<8, false>), grid, dim3(KS_THREADS), 0, s, c->dp, xb, x_stride,
+                                       raised, nullptr, 0, ks, acc, B);
+            }
             LC_HIP(c, hipGetLastError());
             const u64 *c0rest = (G.c0src && !c0_fold) ? G.c0src + b0 * G.c0_stride : nullptr;
-            if (fused && np <= 6) {
+            if (fused && np <= MAX_NP) {
                 // ModDown in two transforms: the inverse one scales P limb k by
                 // N^-1 (P / p_k)^-1 (in place in acc); the forward one computes
-                // the conversion to the Q limbs in its first pass and, unless
-                // permuted c0 terms remain, the combine in its last
+                // the conversion to the Q limbs in its first pass (K products
+                // below 0.875 q each: the sum stays below 7 q for K <= 8) and,
+                // unless permuted c0 terms remain, the combine in its last
                 PolyBatch ib{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0};
                 ib.iscale = c->dp.ks_scale;
                 ib.out_f64 = 1;

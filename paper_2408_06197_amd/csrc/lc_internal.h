@@ -125,7 +125,7 @@ struct Ctx {
         int mac_cycle_min = 16;  // ... when the tile cycles are at least this long
         int mac_cycle_cts = 8;   // ciphertexts per cycle-walk workgroup (8 or 16)
         int mac_short_cts = 16;  // ciphertexts per short-cycle workgroup (8 or 16)
-        int mac_cycle_c0 = 1;    // the walk also folds sum_t phi_t(c0) into the accumulator
+        int mac_cycle_c0 = 1;    // the inner product (walk or gather) also folds sum_t phi_t(c0) into the accumulator
         int mac_cycle_short = 1; // blocks whose tile cycles are at most 2 tiles long skip the walk
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
         int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16

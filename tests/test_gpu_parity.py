@@ -52,6 +52,7 @@ def make_pair(L, O, log_n, qb, pb, seed, steps=(), log_m=0):
 TINY = (5, (30, 28, 28), (30,))
 TINY_A2 = (6, (45, 40, 40, 40, 40), (46, 46))
 CFG1 = (synth.CFG1.log_n, synth.CFG1.q_bits, synth.CFG1.p_bits)
+K8 = (10, (50,) * 16, (50,) * 8)  # eight special primes: digits of 8 limbs (dnum 2), ModDown from 8 limbs
 
 
 # ---- NTT ---------------------------------------------------------------------
@@ -270,7 +271,7 @@ def test_relin_bitexact(torch, L, oracle_mod, prm):
         assert np.array_equal(got[i], ora.relin(t3[i], keys["rlk"])), i
 
 
-@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1])
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1, K8])
 def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm):
     O = oracle_mod
     steps = [1, 2, 5, -3]
@@ -285,7 +286,7 @@ def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm):
 
 
 @pytest.mark.parametrize("plan", ["ones", "twos", "three"])
-@pytest.mark.parametrize("prm", [TINY, TINY_A2])
+@pytest.mark.parametrize("prm", [TINY, TINY_A2, K8])
 def test_rotate_sum_bitexact(torch, L, oracle_mod, prm, plan):
     O = oracle_mod
     levels = prm[0] - 1
