@@ -376,6 +376,42 @@ def plans_for(log_n):
     return [[1] * levels, [2] * (levels // 2) + [1] * (levels % 2), [3] * (levels // 3) + ([levels % 3] if levels % 3 else [])]
 
 
+def graph_form(torch, fn, outs, pairs):
+    """fn (library calls on torch's current stream) captured into a HIP graph
+    on a stream of its own after a warm-up call there has grown that stream's
+    workspaces; three replays, with eager work between them, must equal the
+    eager result before the replays are timed."""
+    sg = torch.cuda.Stream()
+    res = {"ms": None, "replays_equal_eager": False}
+    with torch.cuda.stream(sg):
+        fn()
+        sg.synchronize()
+        want = [t.clone() for t in outs]
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=sg):
+                fn()
+            ok = True
+            for rep in range(3):
+                if rep == 1:
+                    fn()
+                for t in outs:
+                    t.fill_(-1)
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                ok &= all(bool(torch.equal(a, b)) for a, b in zip(outs, want))
+            res["replays_equal_eager"] = ok
+            if ok:
+                ms = event_time(torch, g.replay, reps=10)
+                res.update({"ms": ms, "distances_per_s": pairs / (ms / 1e3)})
+            del g
+        except Exception as e:  # capture is optional; the eager figure stands
+            res["error"] = str(e)
+    torch.cuda.synchronize()
+    return res
+
+
 def small_config(torch, L, synth, w):
     """A smaller workload at full size on the GPU, in every form: device
     ingest; the batched pipeline (lc_pairwise_sqdist) under each hoisting
@@ -417,6 +453,7 @@ def small_config(torch, L, synth, w):
     ms, plan = best
     srv.pairwise_sqdist(cts, plan=plan, out=dist)
     res["batched"] = {"plan": plan, "ms": ms, "distances_per_s": P / (ms / 1e3), "max_rel_err_vs_fp64": rel_err(dist)}
+    res["batched_graph"] = graph_form(torch, lambda: srv.pairwise_sqdist(cts, plan=plan, out=dist), [dist], P)
     pidx = [(a, b) for a in range(n) for b in range(a + 1, n)]
     tmp = torch.empty((1, 2, nq, N), dtype=torch.int64, device="cuda")
     sq = torch.empty((1, 3, nq, N), dtype=torch.int64, device="cuda")
@@ -457,6 +494,10 @@ def small_config(torch, L, synth, w):
     got = kgc.crt_to_double(dec) / scale ** 2
     res["sumdis_per_client"] = {"ms": t_sd, "key_switch_chains": n,
                                 "max_rel_err_vs_fp64": float(np.max(np.abs(got - D.sum(1)) / D.sum(1)))}
+    gf = res["batched_graph"]
+    if gf.get("ms"):
+        log(f"[bench] {w.name}: batched as a HIP graph {gf['ms']:.3f} ms ({gf['distances_per_s']:.0f} distances/s, "
+            f"replays equal the eager result: {gf['replays_equal_eager']})")
     log(f"[bench] {w.name}: batched {ms:.2f} ms ({P / (ms / 1e3):.0f} distances/s, plan {plan}); per-op "
         f"{res['per_op_lazy']['ms']:.1f} ms, eager relin {res['per_op_eager']['ms']:.1f} ms "
         f"({res['lazy_vs_eager_speedup']:.1f}x); max rel err {res['batched']['max_rel_err_vs_fp64']:.1e}")
