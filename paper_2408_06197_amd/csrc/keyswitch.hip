@@ -227,7 +227,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     constexpr int TT = KS_CYC_TILE;
     constexpr int XD = FOLD ? D + 1 : D;     // staged rows per ciphertext: D digits (and c0)
     __shared__ double xt[CB * XD * TT];      // [CB][XD][TT]: source tile c_p
-    __shared__ double kt[R * 2 * D * TT];    // [R][2 D][TT]: keys of the outputs c_{p-1} .. c_{p-R}
+    __shared__ __attribute__((aligned(16))) double kt[R * 2 * D * TT];  // [R][D][TT][2]: keys of the outputs c_{p-1} .. c_{p-R}
     const int u = threadIdx.x, bl = threadIdx.y;
     u32 bx, by, bz;
     mac_block_ids(remap, bx, by, bz);
@@ -283,7 +283,9 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
         for (int d = 0; d < XD; d++) xt[(bl * XD + d) * TT + u] = u64_to_d(xv[d]);
         if (bl < R) {
 #pragma unroll
-            for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
+            for (int d = 0; d < D; d++)  // both components of a digit in one 16-byte word
+                reinterpret_cast<double2 *>(kt)[(bl * D + d) * TT + u] =
+                    make_double2(u64_to_d(kv[2 * d]), u64_to_d(kv[2 * d + 1]));
             pt[bl * TT + u] = pk & (TT - 1);
         }
     };
@@ -302,13 +304,14 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
             const int m = p - t;
             if (m >= sg.m0 && m < sg.m0 + sg.cnt) {
                 const double *xs = xt + bl * XD * TT + pt[(t - 1) * TT + u];
-                const double *kk = kt + (t - 1) * 2 * D * TT + u;
+                const double2 *kk = reinterpret_cast<const double2 *>(kt) + (t - 1) * D * TT + u;
                 double a0 = A[t - 1][0], a1 = A[t - 1][1];
 #pragma unroll
                 for (int d = 0; d < D; d++) {
                     const double xd = xs[d * TT];
-                    a0 += mulmod_d(xd, kk[(2 * d) * TT], q, qinv);
-                    a1 += mulmod_d(xd, kk[(2 * d + 1) * TT], q, qinv);
+                    const double2 kd = kk[d * TT];
+                    a0 += mulmod_d(xd, kd.x, q, qinv);
+                    a1 += mulmod_d(xd, kd.y, q, qinv);
                     if ((d & 3) == 3) {
                         a0 = reduce_d(a0, q, qinv);
                         a1 = reduce_d(a1, q, qinv);
@@ -348,7 +351,7 @@ mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     constexpr int TT = KS_CYC_TILE;
     constexpr int XD = FOLD ? D + 1 : D;
     __shared__ double xt[LM * CB * XD * TT];  // [LM][CB][XD][TT]: the cycle's source tiles
-    __shared__ double kt[R * 2 * D * TT];     // [R][2 D][TT]: keys of one output tile
+    __shared__ __attribute__((aligned(16))) double kt[R * 2 * D * TT];  // [R][D][TT][2]: keys of one output tile
     const int u = threadIdx.x, bl = threadIdx.y;
     u32 bx, by, bz;
     mac_block_ids(remap, bx, by, bz);
@@ -395,7 +398,9 @@ mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     auto store_keys = [&]() {
         if (bl < R) {
 #pragma unroll
-            for (int dk = 0; dk < 2 * D; dk++) kt[(bl * 2 * D + dk) * TT + u] = u64_to_d(kv[dk]);
+            for (int d = 0; d < D; d++)  // both components of a digit in one 16-byte word
+                reinterpret_cast<double2 *>(kt)[(bl * D + d) * TT + u] =
+                    make_double2(u64_to_d(kv[2 * d]), u64_to_d(kv[2 * d + 1]));
             pt[bl * TT + u] = pk & (TT - 1);
         }
     };
@@ -435,12 +440,13 @@ mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
         for (int t = 1; t <= R; t++) {
             const int i = LM == 1 ? 0 : (m + t) % L;  // output c_m reads source tile c_{m+t}
             const double *xs = xt + (i * CB + bl) * XD * TT + pt[(t - 1) * TT + u];
-            const double *kk = kt + (t - 1) * 2 * D * TT + u;
+            const double2 *kk = reinterpret_cast<const double2 *>(kt) + (t - 1) * D * TT + u;
 #pragma unroll
             for (int d = 0; d < D; d++) {
                 const double xd = xs[d * TT];
-                a0 += mulmod_d(xd, kk[(2 * d) * TT], q, qinv);
-                a1 += mulmod_d(xd, kk[(2 * d + 1) * TT], q, qinv);
+                const double2 kd = kk[d * TT];
+                a0 += mulmod_d(xd, kd.x, q, qinv);
+                a1 += mulmod_d(xd, kd.y, q, qinv);
                 if ((d & 3) == 3) {
                     a0 = reduce_d(a0, q, qinv);
                     a1 = reduce_d(a1, q, qinv);
