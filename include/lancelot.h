@@ -374,7 +374,9 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * caller's stream and a second stream of the library's, made on the first
  * such call on that caller stream, forked after the triples and joined
  * before SumDis, so that batches overlap; 1 = all on the caller's stream),
- * "mac_xcd" (1 = the walking and short-cycle inner-product workgroups that
+ * "hoist_multi" (1 = lc_rotate_hoisted from N = 2^10 on stages each
+ * source tile of the raised digits once for up to 8 keys; 0 = one gather per
+ * key), "mac_xcd" (1 = the walking and short-cycle inner-product workgroups that
  * read the same key tiles for different ciphertexts are dispatched to one
  * XCD back to back, so the keys come from that XCD's L2 after the first
  * read; 0 = plain grid order).

@@ -668,6 +668,24 @@ int lc_rotate_hoisted(lc_ctx *x, const uint64_t *ct, size_t count, const int *st
     const u64 S = (u64)c->nq * c->N;
     if (overlap(ct, count * 2 * S * 8, outs, count * nsteps * 2 * S * 8))
         return fail(c, LC_EINVAL, "output must not overlap the input");
+    // the source-major inner product when every key's automorphism acts on
+    // tiles and the key switch takes the fused transforms
+    bool multi = c->tune.hoist_multi && c->tune.mac_cycle_c0 && c->tune.fuse_modup && c->log_n >= 10 &&
+                 c->log_n <= 17 && c->np <= MAX_NP && c->dnum <= 8;
+    std::vector<const u64 *> mkeys(nsteps);
+    std::vector<const u32 *> mperms(nsteps), minv(nsteps);
+    for (int t = 0; t < nsteps && multi; t++) {
+        auto it = c->rot.find(galois_of_step(c->log_n, steps[t]));
+        if (it == c->rot.end()) break;  // reported below
+        auto cy = c->cycles.find(it->first);
+        if (!it->second.perm || cy == c->cycles.end() || !cy->second.inv_tile) {
+            multi = false;
+            break;
+        }
+        mkeys[t] = it->second.ksk;
+        mperms[t] = it->second.perm;
+        minv[t] = cy->second.inv_tile;
+    }
     std::vector<KsGroup> groups(nsteps);
     for (int t = 0; t < nsteps; t++) {
         u64 g = galois_of_step(c->log_n, steps[t]);
@@ -683,6 +701,9 @@ int lc_rotate_hoisted(lc_ctx *x, const uint64_t *ct, size_t count, const int *st
         G.out = outs + (u64)t * 2 * S;
         G.out_stride = (u64)nsteps * 2 * S;
     }
+    if (multi)
+        return keyswitch_rotations(c, ct, count, mkeys.data(), mperms.data(), minv.data(), nsteps, outs,
+                                   (u64)nsteps * 2 * S, (hipStream_t)stream);
     return keyswitch_hoisted(c, ct + S, 2 * S, count, groups.data(), nsteps, (hipStream_t)stream);
 }
 
@@ -1085,6 +1106,9 @@ int lc_set_tuning(lc_ctx *x, const char *name, int value)
     } else if (k == "ks_streams") {
         if (value != 1 && value != 2) return fail(c, LC_EINVAL, "ks_streams: 1/2");
         c->tune.ks_streams = value;
+    } else if (k == "hoist_multi") {
+        if (value != 0 && value != 1) return fail(c, LC_EINVAL, "hoist_multi: 0/1");
+        c->tune.hoist_multi = value;
     } else if (k == "mac_xcd") {
         if (value != 0 && value != 1) return fail(c, LC_EINVAL, "mac_xcd: 0/1");
         c->tune.mac_xcd = value;

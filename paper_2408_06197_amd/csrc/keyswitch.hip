@@ -525,6 +525,93 @@ static void launch_mac_cycle(const Ctx *c, int R, u64 nseg, hipStream_t s, const
     }
 }
 
+// ---- literal hoisted rotations: one staging of each source tile for all keys --
+//
+// Every key of the call maps aligned tiles of KS_CYC_TILE coefficients onto
+// aligned tiles (checked at key set-up), and output tile o of key t reads
+// source tile tau_t(o) at the in-tile positions of its permutation.  A
+// workgroup owns one source tile s of one limb for CB ciphertexts: it stages
+// the tile's digits (and c0) in LDS once, then for each key t computes output
+// tile tau_t^-1(s) of that key from it (the next key's values and indices
+// load while the current key multiplies).  acc is [key][ct][2][ne][N].  Same
+// FP64 Barrett products as the other inner products, and with FOLD the
+// permuted c0 times P mod q joins accumulator 0 of the Q limbs.
+struct MultiKeys {
+    const u64 *key[MULTI_KEYS];
+    const u32 *perm[MULTI_KEYS];
+    const u32 *inv[MULTI_KEYS];  // source tile -> output tile of the key
+    int n;
+};
+
+template <int D, int CB, bool FOLD>
+__global__ void __launch_bounds__(KS_CYC_TILE * CB)
+mac_multi_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
+                 MultiKeys mk, u64 *acc, u64 count, int remap, u32 nx)
+{
+    constexpr int TT = KS_CYC_TILE;
+    constexpr int XD = FOLD ? D + 1 : D;
+    __shared__ double xt[CB * XD * TT];  // [CB][XD][TT]: the source tile
+    const int u = threadIdx.x, bl = threadIdx.y;
+    u32 bx, by, bz;
+    mac_block_ids(remap, bx, by, bz);
+    if (bx >= nx) return;  // launch padding
+    const u32 st = bx;     // source tile
+    const int l = (int)by;
+    const u64 b = (u64)bz * CB + bl;
+    const bool live = b < count;
+    const u64 N = dp.N, NE = (u64)dp.ne * N, lN = (u64)l * N;
+    const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
+    const int own = l < dp.nq ? l / dp.alpha : -1;
+    const bool fold = FOLD && l < dp.nq;
+    const double pq = fold ? u64_to_d(dp.pmod[l]) : 0.0;
+    {
+        const u64 src = (u64)st * TT + u;
+        u64 xv[XD];
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            xv[d] = live ? (d == own ? x[b * x_stride + lN + src] : raised[((b * D + d) * dp.ne + l) * N + src]) : 0;
+        if (FOLD) xv[XD - 1] = (live && fold) ? c0[b * c0_stride + lN + src] : 0;
+#pragma unroll
+        for (int d = 0; d < XD; d++) xt[(bl * XD + d) * TT + u] = u64_to_d(xv[d]);
+    }
+    __syncthreads();
+    const double *xs0 = xt + bl * XD * TT;
+    u64 kv[2 * D];
+    u32 pin = 0;
+    u64 j = 0;
+    auto fetch = [&](int t) {
+        const u64 o = ((const gu32 *)mk.inv[t])[st];  // uniform over the workgroup
+        j = o * TT + u;
+        pin = ((const gu32 *)mk.perm[t])[j] & (TT - 1);
+        const gu64 *kp = (const gu64 *)mk.key[t] + lN + j;
+#pragma unroll
+        for (int dk = 0; dk < 2 * D; dk++) kv[dk] = kp[(u64)dk * NE];
+    };
+    fetch(0);
+    for (int t = 0; t < mk.n; t++) {
+        double k[2 * D];
+#pragma unroll
+        for (int dk = 0; dk < 2 * D; dk++) k[dk] = u64_to_d(kv[dk]);
+        const u32 p0 = pin;
+        const u64 j0 = j;
+        if (t + 1 < mk.n) fetch(t + 1);
+        const double *xs = xs0 + p0;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const double xd = xs[d * TT];
+            a0 += mulmod_d(xd, k[2 * d], q, qinv);
+            a1 += mulmod_d(xd, k[2 * d + 1], q, qinv);
+        }
+        if (FOLD && fold) a0 += mulmod_d(xs[(XD - 1) * TT], pq, q, qinv);
+        if (live) {
+            u64 *o = acc + (((u64)t * count + b) * 2) * NE + lN + j0;
+            o[0] = d_to_canonical(reduce_d(a0, q, qinv), q, qinv);
+            o[NE] = d_to_canonical(reduce_d(a1, q, qinv), q, qinv);
+        }
+    }
+}
+
 int build_cycle_table(Ctx *c, u64 g)
 {
     if (c->cycles.count(g)) return LC_OK;
@@ -559,12 +646,17 @@ int build_cycle_table(Ctx *c, u64 g)
                     segs.push_back(CycleSeg{base, len, m0, std::min(KS_CYC_SEG, len - m0)});
             }
             if (walk.size() == nt) {  // tau is a permutation of the tiles
+                std::vector<u32> inv(nt);
+                for (u64 o = 0; o < nt; o++) inv[tau[o]] = (u32)o;
                 u32 *dw = (u32 *)dev_alloc(c, walk.size() * sizeof(u32));
                 CycleSeg *ds = (CycleSeg *)dev_alloc(c, segs.size() * sizeof(CycleSeg));
-                if (!dw || !ds) return fail(c, LC_ENOMEM, "cycle table allocation failed");
+                u32 *di = (u32 *)dev_alloc(c, nt * sizeof(u32));
+                if (!dw || !ds || !di) return fail(c, LC_ENOMEM, "cycle table allocation failed");
                 LC_HIP(c, hipMemcpy(dw, walk.data(), walk.size() * sizeof(u32), hipMemcpyHostToDevice));
                 LC_HIP(c, hipMemcpy(ds, segs.data(), segs.size() * sizeof(CycleSeg), hipMemcpyHostToDevice));
-                c->table_bytes += walk.size() * sizeof(u32) + segs.size() * sizeof(CycleSeg);
+                LC_HIP(c, hipMemcpy(di, inv.data(), nt * sizeof(u32), hipMemcpyHostToDevice));
+                c->table_bytes += walk.size() * sizeof(u32) + segs.size() * sizeof(CycleSeg) + nt * sizeof(u32);
+                tab.inv_tile = di;
                 tab.walk = dw;
                 tab.segs = ds;
                 tab.nseg = (int)segs.size();
@@ -648,6 +740,57 @@ int keyswitch_hoisted(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGro
     return keyswitch_hoisted_ws(c, x, x_stride, count, groups, ngroups, ws, per_ct * chunk, s);
 }
 
+// ModUp of B inputs (limbs at x, stride x_stride, NTT domain) into the raised
+// digits: the inverse transform reads the input limbs in place (out of place
+// into xhat); its last pass scales limb a by N^-1 (Q_d/q_a)^-1, leaving the
+// ModUp digits y_a; the forward transform of the raised limbs computes their
+// base conversion in its first pass.
+static int modup_fused(Ctx *c, const u64 *xb, u64 x_stride, u64 B, u64 *xhat, u64 *raised, hipStream_t s)
+{
+    const u64 N = c->N;
+    PolyBatch ib{xhat, B, c->nq, (u64)c->nq, 0, 0};
+    ib.iscale = c->dp.ks_scale;
+    ib.out_f64 = 1;
+    ib.in_base = xb;
+    ib.in_gstride = x_stride / N;
+    int rc = launch_ntt_inv(c, ib, s);
+    if (rc) return rc;
+    PolyBatch fb{raised, B * c->dnum, c->ne, (u64)c->ne, 0, 1};
+    fb.conv = 1;
+    fb.conv_y = xhat;
+    fb.conv_stride = (u64)c->nq * N;
+    return launch_ntt_fwd(c, fb, s);
+}
+
+// ModDown of B accumulators acc [B][2][ne][N] in two transforms: the inverse
+// one scales P limb k by N^-1 (P / p_k)^-1 (in place in acc); the forward one
+// of v computes the conversion to the Q limbs in its first pass (K products
+// below 0.875 q each: the sum stays below 7 q for K <= 8) and, when out is
+// given, the combine out = (acc - v) P^-1 (+ base) in its last pass.
+static int moddown_fused(Ctx *c, u64 *acc, u64 B, u64 *v, const u64 *base, u64 base_stride, u64 *out,
+                         u64 out_stride, hipStream_t s)
+{
+    const u64 N = c->N;
+    PolyBatch ib{acc + (u64)c->nq * N, B * 2, c->np, (u64)c->ne, c->nq, 0};
+    ib.iscale = c->dp.ks_scale;
+    ib.out_f64 = 1;
+    int rc = launch_ntt_inv(c, ib, s);
+    if (rc) return rc;
+    PolyBatch fb{v, B * 2, c->nq, (u64)c->nq, 0, 0};
+    fb.conv = 2;
+    fb.conv_y = acc + (u64)c->nq * N;
+    fb.conv_stride = (u64)c->ne * N;
+    if (out) {
+        fb.comb_acc = acc;
+        fb.comb_acc_stride = (u64)c->ne * N;
+        fb.comb_add = base;
+        fb.comb_add_stride = base_stride;
+        fb.comb_out = out;
+        fb.comb_out_stride = out_stride;
+    }
+    return launch_ntt_fwd(c, fb, s);
+}
+
 int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const KsGroup *groups, int ngroups,
                          u64 *ws, u64 ws_words, hipStream_t s)
 {
@@ -674,22 +817,7 @@ int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const Ks
             LC_HIP(c, hipGetLastError());
         }
         if (fused) {
-            // the inverse transform reads the input limbs in place (out of
-            // place into xhat); its last pass scales limb a by
-            // N^-1 (Q_d/q_a)^-1, leaving the ModUp digits y_a; the forward
-            // transform of the raised limbs computes their base conversion
-            // in its first pass
-            PolyBatch ib{xhat, B, nq, (u64)nq, 0, 0};
-            ib.iscale = c->dp.ks_scale;
-            ib.out_f64 = 1;
-            ib.in_base = xb;
-            ib.in_gstride = x_stride / N;
-            if ((rc = launch_ntt_inv(c, ib, s))) return rc;
-            PolyBatch fb{raised, B * dnum, ne, (u64)ne, 0, 1};
-            fb.conv = 1;
-            fb.conv_y = xhat;
-            fb.conv_stride = (u64)nq * N;
-            if ((rc = launch_ntt_fwd(c, fb, s))) return rc;
+            if ((rc = modup_fused(c, xb, x_stride, B, xhat, raised, s))) return rc;
         } else {
             if ((rc = launch_ntt_inv(c, PolyBatch{xhat, B, nq, (u64)nq, 0, 0}, s))) return rc;
             const u32 tpb = (u32)std::min<u64>(N, KS_THREADS);
@@ -736,28 +864,11 @@ int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const Ks
             LC_HIP(c, hipGetLastError());
             const u64 *c0rest = (G.c0src && !c0_fold) ? G.c0src + b0 * G.c0_stride : nullptr;
             if (fused && np <= MAX_NP) {
-                // ModDown in two transforms: the inverse one scales P limb k by
-                // N^-1 (P / p_k)^-1 (in place in acc); the forward one computes
-                // the conversion to the Q limbs in its first pass (K products
-                // below 0.875 q each: the sum stays below 7 q for K <= 8) and,
-                // unless permuted c0 terms remain, the combine in its last
-                PolyBatch ib{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0};
-                ib.iscale = c->dp.ks_scale;
-                ib.out_f64 = 1;
-                if ((rc = launch_ntt_inv(c, ib, s))) return rc;
-                PolyBatch fb{v, B * 2, nq, (u64)nq, 0, 0};
-                fb.conv = 2;
-                fb.conv_y = acc + (u64)nq * N;
-                fb.conv_stride = (u64)ne * N;
-                if (!c0rest) {
-                    fb.comb_acc = acc;
-                    fb.comb_acc_stride = (u64)ne * N;
-                    fb.comb_add = G.base ? G.base + b0 * G.base_stride : nullptr;
-                    fb.comb_add_stride = G.base_stride;
-                    fb.comb_out = G.out + b0 * G.out_stride;
-                    fb.comb_out_stride = G.out_stride;
-                }
-                if ((rc = launch_ntt_fwd(c, fb, s))) return rc;
+                // unless permuted c0 terms remain, the combine runs in the
+                // ModDown's last pass
+                if ((rc = moddown_fused(c, acc, B, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride,
+                                        c0rest ? nullptr : G.out + b0 * G.out_stride, G.out_stride, s)))
+                    return rc;
                 if (!c0rest) continue;
             } else {
                 if ((rc = launch_ntt_inv(c, PolyBatch{acc + (u64)nq * N, B * 2, np, (u64)ne, nq, 0}, s))) return rc;
@@ -770,6 +881,75 @@ int keyswitch_hoisted_ws(Ctx *c, const u64 *x, u64 x_stride, u64 count, const Ks
                                c->dp, acc, v, G.base ? G.base + b0 * G.base_stride : nullptr, G.base_stride, c0rest,
                                G.c0_stride, ks, G.out + b0 * G.out_stride, G.out_stride, B);
             LC_HIP(c, hipGetLastError());
+        }
+    }
+    return LC_OK;
+}
+
+// Literal hoisted rotations through the source-major inner product: per
+// batch one ModUp, then per group of up to MULTI_KEYS keys one inner product
+// that stages each source tile once, and one fused ModDown per key (the
+// permuted c0 is folded into the inner product, so its last pass writes the
+// rotated ciphertext).  keys / perms / inv are per step; outs[t] of ct b is at
+// out + b * out_stride + t * 2 S.
+int keyswitch_rotations(Ctx *c, const u64 *ct, u64 count, const u64 *const *keys, const u32 *const *perms,
+                        const u32 *const *inv, int nsteps, u64 *out, u64 out_stride, hipStream_t s)
+{
+    const u64 N = c->N, S = (u64)c->nq * N;
+    const int nq = c->nq, ne = c->ne, dnum = c->dnum;
+    if (dnum > 8 || nsteps < 1) return fail(c, LC_EINVAL, "source-major rotations need 1 <= dnum <= 8 and a step");
+    const int rk = std::min(nsteps, MULTI_KEYS);
+    const u64 per_ct = ((u64)nq + (u64)dnum * ne + (u64)rk * 2 * ne + 2ull * nq) * N;
+    u64 chunk = std::min<u64>(count, (u64)c->tune.ks_chunk);
+    if (c->ws_limit) chunk = std::max<u64>(1, std::min<u64>(chunk, c->ws_limit / (per_ct * 8)));
+    u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk, s);
+    if (!ws) return LC_ENOMEM;
+    constexpr int CB = 8;
+    int rc;
+    for (u64 b0 = 0; b0 < count; b0 += chunk) {
+        const u64 B = std::min(chunk, count - b0);
+        u64 *xhat = ws;
+        u64 *raised = xhat + B * nq * N;
+        u64 *acc = raised + B * dnum * ne * N;
+        u64 *v = acc + (u64)rk * B * 2 * ne * N;
+        const u64 *cb = ct + b0 * 2 * S;
+        if ((rc = modup_fused(c, cb + S, 2 * S, B, xhat, raised, s))) return rc;
+        for (int t0 = 0; t0 < nsteps; t0 += rk) {
+            MultiKeys mk{};
+            mk.n = std::min(rk, nsteps - t0);
+            for (int t = 0; t < mk.n; t++) {
+                mk.key[t] = keys[t0 + t];
+                mk.perm[t] = perms[t0 + t];
+                mk.inv[t] = inv[t0 + t];
+            }
+            dim3 grid((u32)(N / KS_CYC_TILE), (u32)ne, (u32)((B + CB - 1) / CB));
+            const u32 nx = grid.x;
+            const int remap = c->tune.mac_xcd && grid.z > 1;
+            if (remap) {
+                const u32 m = 8u / std::gcd(grid.y, 8u);
+                grid.x = (grid.x + m - 1) / m * m;
+            }
+            const dim3 block(KS_CYC_TILE, CB);
+#define LC_MULTI(DD)                                                                                              \
+    hipLaunchKernelGGL((mac_multi_kernel<DD, CB, true>), grid, block, 0, s, c->dp, cb + S, 2 * S, raised, cb, 2 * S, \
+                       mk, acc, B, remap, nx)
+            switch (dnum) {
+            case 1: LC_MULTI(1); break;
+            case 2: LC_MULTI(2); break;
+            case 3: LC_MULTI(3); break;
+            case 4: LC_MULTI(4); break;
+            case 5: LC_MULTI(5); break;
+            case 6: LC_MULTI(6); break;
+            case 7: LC_MULTI(7); break;
+            default: LC_MULTI(8); break;
+            }
+#undef LC_MULTI
+            LC_HIP(c, hipGetLastError());
+            for (int t = 0; t < mk.n; t++) {
+                u64 *o = out + b0 * out_stride + (u64)(t0 + t) * 2 * S;
+                if ((rc = moddown_fused(c, acc + (u64)t * B * 2 * ne * N, B, v, nullptr, 0, o, out_stride, s)))
+                    return rc;
+            }
         }
     }
     return LC_OK;

@@ -47,6 +47,7 @@ struct DevParams {
 // output positions m0 .. m0 + cnt - 1 of the cycle at walk[base .. base + len).
 constexpr int KS_CYC_TILE = 32;
 constexpr int KS_CYC_SEG = 32;
+constexpr int MULTI_KEYS = 8;  // keys per source-major inner product (literal hoisted rotations)
 struct CycleSeg {
     int base, len, m0, cnt;
 };
@@ -56,6 +57,7 @@ struct CycleTable {
     int nseg = 0;     // 0: the map does not act on tiles (N below the tile size)
     int min_len = 0;  // shortest cycle (all cycles have one length for a power of 5)
     int max_len = 0;  // longest cycle
+    const u32 *inv_tile = nullptr;  // [N / KS_CYC_TILE]: source tile -> output tile (the inverse tile map)
 };
 
 struct RotKey {
@@ -130,6 +132,7 @@ struct Ctx {
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
         int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
         int ks_streams = 2;   // streams the batches of a pairwise finish alternate over (1 or 2)
+        int hoist_multi = 1;  // literal hoisted rotations stage each source tile once for up to 8 keys
         int mac_xcd = 1;      // cycle-walk / short-cycle workgroups sharing key tiles run on one XCD
     } tune;
     size_t table_bytes = 0, key_bytes = 0;
@@ -308,5 +311,10 @@ u64 ks_words_per_ct(const Ctx *c);
 // Builds (once, at key set-up: it copies to the device synchronously) the
 // tile-cycle walk of Galois element g.
 int build_cycle_table(Ctx *c, u64 g);
+// Literal hoisted rotations of count ciphertexts (ct, [count][2][nq][N])
+// through the source-major inner product; needs the fused key-switch path
+// and tile tables for every key.
+int keyswitch_rotations(Ctx *c, const u64 *ct, u64 count, const u64 *const *keys, const u32 *const *perms,
+                        const u32 *const *inv, int nsteps, u64 *out, u64 out_stride, hipStream_t s);
 
 }  // namespace lc

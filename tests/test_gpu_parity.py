@@ -271,11 +271,16 @@ def test_relin_bitexact(torch, L, oracle_mod, prm):
         assert np.array_equal(got[i], ora.relin(t3[i], keys["rlk"])), i
 
 
-@pytest.mark.parametrize("prm", [TINY, TINY_A2, CFG1, K8])
-def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm):
+@pytest.mark.parametrize("prm,multi", [(TINY, 1), (TINY_A2, 1), (CFG1, 1), (CFG1, 0), (K8, 1), (K8, 0)],
+                         ids=["n32", "n64_a2", "n4096", "n4096_per_key", "n1024_k8", "n1024_k8_per_key"])
+def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm, multi):
+    """Literal hoisted rotations against the oracle: from 2^10 on, through the
+    inner product that stages each source tile once for all keys (multi 1)
+    and through one gather per key (multi 0)."""
     O = oracle_mod
     steps = [1, 2, 5, -3]
     ctx, ora, keys = make_pair(L, O, *prm, seed=13, steps=steps)
+    ctx.set_tuning("hoist_multi", multi)
     rng = np.random.default_rng(7)
     m = rng.integers(-(1 << 20), 1 << 20, size=(2, ctx.N), dtype=np.int64)
     cts = ora.encrypt(3, 0, m, keys["pk"])
@@ -528,7 +533,7 @@ def test_set_tuning_rejects_bad_values(L):
     for name, value in (("pair_lanes", 12), ("pair_ppt", 5), ("pair_mfma", 3), ("ks_chunk", 0), ("ntt_sub_kb", -1), ("mac_cts", 4),
                         ("mac_cycle", 2), ("mac_cycle_min", 0), ("fuse_modup", 3), ("ms_shape", 3),
                         ("mac_cycle_cts", 12), ("mac_cycle_c0", 2), ("mac_cycle_short", 2), ("mac_short_cts", 4),
-                        ("ks_streams", 3), ("mac_xcd", 2), ("nope", 1)):
+                        ("ks_streams", 3), ("mac_xcd", 2), ("hoist_multi", 2), ("nope", 1)):
         with pytest.raises(L.LancelotError):
             ctx.set_tuning(name, value)
 
