@@ -290,6 +290,26 @@ def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm, multi):
         assert np.array_equal(got[c], want), c
 
 
+def test_rotate_hoisted_batches_and_key_groups(torch, L, oracle_mod):
+    """The source-major form across its batch and key-group edges: 40
+    ciphertexts (batches of 32 and 8) and 11 steps (key groups of 8 and 3)
+    give the per-key form's bits, and sampled outputs equal the oracle."""
+    O = oracle_mod
+    steps = [1, 2, 3, 4, 5, 7, 16, 64, -1, -9, 1000]
+    ctx, ora, keys = make_pair(L, O, *CFG1, seed=31, steps=steps)
+    cts = synth.uniform_residues(32, ctx.q, (40, 2, ctx.N))
+    g = up(torch, cts)
+    ctx.set_tuning("hoist_multi", 1)
+    multi = down(ctx.rotate_hoisted(g, steps))
+    ctx.set_tuning("hoist_multi", 0)
+    per_key = down(ctx.rotate_hoisted(g, steps))
+    assert np.array_equal(multi, per_key)
+    rks = [keys["rot"][k] for k in steps]
+    for c in (0, 31, 32, 39):
+        want = ora.rotate_hoisted(cts[c], steps, rks)
+        assert np.array_equal(multi[c], want), c
+
+
 @pytest.mark.parametrize("plan", ["ones", "twos", "three"])
 @pytest.mark.parametrize("prm", [TINY, TINY_A2, K8])
 def test_rotate_sum_bitexact(torch, L, oracle_mod, prm, plan):
