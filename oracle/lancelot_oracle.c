@@ -22,11 +22,13 @@
  *   - The extended basis is q_0..q_L followed by p_0..p_{K-1}.
  *
  * Parity status: every function here is pinned by tests/test_oracle_*.py
- * against brute force, closed forms, library routines or invariants, except
- * the bit patterns that follow from conventions the paper leaves open (PRNG
- * stream layout, gadget, fast base conversion, rotate-sum plan); those are
- * "parity unpinned" beyond the invariants their tests check (decryption,
- * linearity, agreement with the exact integer computation within the noise).
+ * against brute force, closed forms, library routines or invariants.  The
+ * bit patterns that follow from conventions the paper leaves open are pinned
+ * too: the PRNG stream layout against numpy's Philox4x64-10, the gadget by
+ * the key-structure identity, and fast base conversion, ModUp, ModDown, key
+ * switching, hoisted rotations and rotate-and-sum (for several plans) bit for
+ * bit against an independent Python big-integer computation at N = 16
+ * (tests/test_oracle_bigint.py).
  */
 #include <stdint.h>
 #include <stdlib.h>
