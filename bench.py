@@ -610,6 +610,8 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     # can grow for 40-client rounds, lc_footprint) and for torch's cache
     ws = max(serve.stream_workspace(ch, 40, k_chunk) for ch in chains.values())
     budget = int(0.5 * (free - args.serve_slots * ws))
+    log(f"[bench] serving: {free / 1e9:.1f} GB free, {args.serve_slots} slots x {ws / 1e9:.1f} GB stream "
+        f"workspace, admission budget {budget / 1e9:.1f} GB")
     names = list(chains)
 
     def progress(k, rec):
@@ -617,10 +619,14 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
             log(f"[bench] serving: {k} rounds done (last: n={rec['n']} dim={rec['dim']} {rec['chain']}, "
                 f"latency {rec['latency']:.3f}s)")
 
+    refused = []
+
     def run(specs):
         ex = serve.GpuExecutor(torch, contexts, pools, chains, plans, k_chunk=k_chunk, streams=args.serve_slots)
-        return serve.Scheduler(chains, budget, slots=args.serve_slots, k_chunk=k_chunk).run(specs, ex,
-                                                                                          on_done=progress)
+        sch = serve.Scheduler(chains, budget, slots=args.serve_slots, k_chunk=k_chunk)
+        rec = sch.run(specs, ex, on_done=progress)
+        refused.extend(sch.refused)
+        return rec
 
     # closed-loop calibration: a burst of rounds arriving together
     calib = serve.make_stream(8, rate=0.0, chains=names, seed=2999)
@@ -634,9 +640,13 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
     log(f"[bench] serving: closed-loop capacity {capacity:.2f} rounds/s; Poisson rate {rate:.2f}/s")
     specs = serve.make_stream(args.serve, rate=rate, chains=names, seed=3000)
     t0 = time.perf_counter()
+    refused.clear()
     rec = run(specs)
     wall = time.perf_counter() - t0
     st = serve.latency_stats(rec)
+    st["refused_rounds"] = list(refused)  # footprint above the whole admission budget: not run
+    if refused:
+        log(f"[bench] serving: {len(refused)} rounds refused (footprint above the budget): {refused}")
     # every tenth round's decrypted distances against FP64
     errs = []
     for rid in sorted(r for r in rec if r % 10 == 0):

@@ -126,6 +126,7 @@ class Scheduler:
         self.k_chunk = k_chunk
         self.used = 0
         self.deferred = 0  # admissions the executor put off for lack of device memory
+        self.refused: List[int] = []  # rounds whose footprint alone exceeds the budget (not run)
         self.active: Dict[int, tuple] = {}
 
     def footprint(self, spec: RoundSpec) -> int:
@@ -155,8 +156,14 @@ class Scheduler:
                 i += 1
             # admit in arrival order while capacity allows; an executor that
             # cannot place a round right now (start returns None) keeps it at
-            # the head of the queue until a running round frees memory
-            while waiting and self.can_admit(waiting[0]):
+            # the head of the queue until a running round frees memory; a
+            # round that could never fit the budget is refused, not run
+            while waiting:
+                if self.footprint(waiting[0]) > self.budget:
+                    self.refused.append(waiting.pop(0).rid)
+                    continue
+                if not self.can_admit(waiting[0]):
+                    break
                 spec = waiting[0]
                 handle = executor.start(spec)
                 if handle is None:

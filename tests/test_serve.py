@@ -96,6 +96,19 @@ def test_round_larger_than_budget_is_refused():
         sch.can_admit(spec)
 
 
+def test_oversize_round_refused_in_stream():
+    """In a stream, a round larger than the whole budget is refused and
+    listed; the rounds around it run."""
+    clock = FakeClock()
+    sch = serve.Scheduler(CH, budget_bytes=1 << 34, slots=2, k_chunk=64)
+    specs = [serve.RoundSpec(i, 0.001 * i, "b", 5, 100_000, 1, "flip5", 1) for i in range(6)]
+    big = serve.RoundSpec(6, 0.0035, "b", 40, 11_200_000, 4, "flip5", 1)
+    assert sch.footprint(big) > sch.budget
+    ex = FakeExecutor(clock, lambda s: 0.01)
+    rec = sch.run(sorted(specs + [big], key=lambda s: s.arrival), ex, clock=clock, sleep=clock.sleep)
+    assert sorted(rec) == list(range(6)) and sch.refused == [6]
+
+
 def test_executor_refusal_defers_round():
     """A round the executor cannot place (start returns None, as on device
     memory pressure) stays at the head of the queue and is started after a
