@@ -605,7 +605,13 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
                                           tails=[t for t in tails if t < ch.slots])
     log(f"[bench] serving: pools encoded in {time.perf_counter() - t0:.1f}s")
     torch.cuda.empty_cache()
-    free, _ = torch.cuda.mem_get_info()
+    torch.cuda.synchronize()
+    # large frees can reach the free-memory count a little later: take the
+    # largest of a few readings
+    free = 0
+    for _ in range(5):
+        free = max(free, torch.cuda.mem_get_info()[0])
+        time.sleep(0.1)
     # leave room for the library's per-stream workspace (the largest a stream
     # can grow for 40-client rounds, lc_footprint) and for torch's cache
     ws = max(serve.stream_workspace(ch, 40, k_chunk) for ch in chains.values())
