@@ -227,9 +227,10 @@ int lc_relin_noalloc(lc_ctx *ctx, const uint64_t *ct3_dev, uint64_t *ct2_dev, si
  * digits, the key inner product and ModDown.  outs [count][nsteps][2][n_q][N],
  * not overlapping ct; 1 <= nsteps <= 64; a missing key gives LC_EKEY.  With
  * "hoist_multi" (default) the stream's key-switch workspace holds the
- * accumulators of up to 8 steps per ciphertext of a batch (at most 32
- * ciphertexts): (n_q + dnum (n_q + n_p) + 2 min(nsteps, 8) (n_q + n_p)
- * + 2 n_q) N words per ciphertext. */
+ * accumulators of up to 8 steps per ciphertext of a batch, and batches are
+ * sized to at most 12 GiB (or the workspace limit):
+ * (n_q + dnum (n_q + n_p) + 2 min(nsteps, 8) (n_q + n_p) + 2 n_q) N words
+ * per ciphertext. */
 int lc_rotate_hoisted(lc_ctx *ctx, const uint64_t *ct_dev, size_t count, const int *steps, int nsteps,
                       uint64_t *outs_dev, void *stream);
 /* Rotate-and-sum in place (Methods, Dynamic Hoisting): after it every slot

@@ -900,10 +900,13 @@ int keyswitch_rotations(Ctx *c, const u64 *ct, u64 count, const u64 *const *keys
     if (dnum > 8 || nsteps < 1) return fail(c, LC_EINVAL, "source-major rotations need 1 <= dnum <= 8 and a step");
     const int rk = std::min(nsteps, MULTI_KEYS);
     const u64 per_ct = ((u64)nq + (u64)dnum * ne + (u64)rk * 2 * ne + 2ull * nq) * N;
-    // batches of at most 32 ciphertexts: the accumulators of 8 keys make a
-    // ciphertext's workspace about 2.3 times that of one key switch, and the
-    // shared staging needs no larger batch
-    u64 chunk = std::min<u64>(count, std::min<u64>((u64)c->tune.ks_chunk, 32));
+    // batches sized to at most 12 GiB of workspace (the accumulators of 8
+    // keys make a ciphertext's workspace about 2.3 times that of one key
+    // switch): all of a small ring's ciphertexts in one batch, whose
+    // launches are then few and large; 35 ciphertexts at N = 2^16 with
+    // 24 + 4 limbs
+    const u64 cap = ((u64)12 << 30) / (per_ct * 8);
+    u64 chunk = std::max<u64>(1, std::min<u64>(count, cap));
     if (c->ws_limit) chunk = std::max<u64>(1, std::min<u64>(chunk, c->ws_limit / (per_ct * 8)));
     u64 *ws = ws_get(c, WS_KS, per_ct * 8 * chunk, s);
     if (!ws) return LC_ENOMEM;

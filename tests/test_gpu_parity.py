@@ -292,15 +292,20 @@ def test_rotate_hoisted_bitexact(torch, L, oracle_mod, prm, multi):
 
 def test_rotate_hoisted_batches_and_key_groups(torch, L, oracle_mod):
     """The source-major form across its batch and key-group edges: 40
-    ciphertexts (batches of 32 and 8) and 11 steps (key groups of 8 and 3)
-    give the per-key form's bits, and sampled outputs equal the oracle."""
+    ciphertexts (a workspace limit that holds 32 of them: batches of 32 and
+    8; without it, one batch) and 11 steps (key groups of 8 and 3) give the
+    per-key form's bits, and sampled outputs equal the oracle."""
     O = oracle_mod
     steps = [1, 2, 3, 4, 5, 7, 16, 64, -1, -9, 1000]
     ctx, ora, keys = make_pair(L, O, *CFG1, seed=31, steps=steps)
     cts = synth.uniform_residues(32, ctx.q, (40, 2, ctx.N))
     g = up(torch, cts)
     ctx.set_tuning("hoist_multi", 1)
+    whole = down(ctx.rotate_hoisted(g, steps))
+    per_ct = (ctx.nq + ctx.dnum * ctx.ne + 2 * 8 * ctx.ne + 2 * ctx.nq) * ctx.N * 8
+    ctx.set_workspace_limit(32 * per_ct)
     multi = down(ctx.rotate_hoisted(g, steps))
+    assert np.array_equal(multi, whole)
     ctx.set_tuning("hoist_multi", 0)
     per_key = down(ctx.rotate_hoisted(g, steps))
     assert np.array_equal(multi, per_key)
