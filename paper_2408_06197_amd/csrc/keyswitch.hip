@@ -178,6 +178,26 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u6
     }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin in dispatch order (x
+// fastest).  With remap set (the launch pads gx so that gx * gy is a
+// multiple of 8; workgroups with x past the real count return at once), the
+// gz workgroups that share (x, y) -- the same key tiles, for different
+// ciphertexts -- are made consecutive on one XCD, so all but the first find
+// the keys in its L2.
+__device__ __forceinline__ void mac_block_ids(int remap, u32 &bx, u32 &by, u32 &bz)
+{
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+    if (!remap) return;
+    const u32 gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const u32 lin = bx + gx * (by + gy * bz);
+    const u32 j = lin >> 3, xy = (j / gz) * 8 + (lin & 7);
+    bz = j % gz;
+    bx = xy % gx;
+    by = xy / gx;
+}
+
 // ---- cycle-walking inner product for a hoisted block ------------------------
 //
 // The keys of a rotate-and-sum block are the powers phi^1 .. phi^R of one
@@ -199,26 +219,6 @@ mac_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u6
 // same source tiles, so it is staged with the digits and added to the Q
 // limbs of accumulator 0 times P mod q (exact after ModDown, which divides
 // by P), and the combine kernel skips its per-key gathers of c0.
-// Workgroups are dealt to the 8 XCDs round-robin in dispatch order (x
-// fastest).  With remap set (the launch pads gx so that gx * gy is a
-// multiple of 8; workgroups with x past the real count return at once), the
-// gz workgroups that share (x, y) -- the same key tiles, for different
-// ciphertexts -- are made consecutive on one XCD, so all but the first find
-// the keys in its L2.
-__device__ __forceinline__ void mac_block_ids(int remap, u32 &bx, u32 &by, u32 &bz)
-{
-    bx = blockIdx.x;
-    by = blockIdx.y;
-    bz = blockIdx.z;
-    if (!remap) return;
-    const u32 gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-    const u32 lin = bx + gx * (by + gy * bz);
-    const u32 j = lin >> 3, xy = (j / gz) * 8 + (lin & 7);
-    bz = j % gz;
-    bx = xy % gx;
-    by = xy / gx;
-}
-
 template <int R, int D, int CB, bool FOLD>
 __global__ void __launch_bounds__(KS_CYC_TILE * CB, CB == 8 ? 3 : 1)
 mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, const u64 *c0, u64 c0_stride,
@@ -227,7 +227,8 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
     constexpr int TT = KS_CYC_TILE;
     constexpr int XD = FOLD ? D + 1 : D;     // staged rows per ciphertext: D digits (and c0)
     __shared__ double xt[CB * XD * TT];      // [CB][XD][TT]: source tile c_p
-    __shared__ __attribute__((aligned(16))) double kt[R * 2 * D * TT];  // [R][D][TT][2]: keys of the outputs c_{p-1} .. c_{p-R}
+    // [R][D][TT][2]: keys of the outputs c_{p-1} .. c_{p-R}
+    __shared__ __attribute__((aligned(16))) double kt[R * 2 * D * TT];
     const int u = threadIdx.x, bl = threadIdx.y;
     u32 bx, by, bz;
     mac_block_ids(remap, bx, by, bz);
