@@ -37,8 +37,8 @@ A2_OPS_PER_UPDATE = 23
 # (FETCH_SIZE 2.0x low, WRITE_SIZE exact); see
 # profiles/pair_triples_n65536_l24_20clients_pmc.txt.  Valid only for the
 # kernel source it was taken on: the section of ops.hip is hashed at run time.
-A2_PMC = {"fetch_bytes": 2.0 * 84056410 * 1024, "write_bytes": 7004160 * 1024,
-          "source_sha256": "5b5a34a91618e8776927f8698e52347a8cf00493ef266cfd99cd7c5873385b4b"}
+A2_PMC = {"fetch_bytes": 2.0 * 84056392 * 1024, "write_bytes": 7004160 * 1024,
+          "source_sha256": "3844a40c5187beb1493f22bd107fa53f981d017b1b830998616b543e8387f78d"}
 A2_SECTION = ("ops.hip", "// ---- fused subtract / square / lazy accumulate over all pairs", "// ---- SumDis[i]")
 # The same for the forward NTT's two launches on 64 ciphertexts' limbs
 # (1536 limb-polynomials at N = 2^16): `python -m
