@@ -634,8 +634,10 @@ def serve_bench(args, torch, L, srv16, kgc16, plan16):
         refused.extend(sch.refused)
         return rec
 
-    # closed-loop calibration: a burst of rounds arriving together
-    calib = serve.make_stream(8, rate=0.0, chains=names, seed=2999)
+    # closed-loop calibration: a burst of 24 rounds arriving together (the
+    # class mix of a shorter burst, and with it the capacity, varied from run
+    # to run)
+    calib = serve.make_stream(24, rate=0.0, chains=names, seed=2999)
     t0 = time.perf_counter()
     rec = run(calib)
     torch.cuda.synchronize()
