@@ -213,8 +213,12 @@ __device__ __forceinline__ void mac_block_ids(int remap, u32 &bx, u32 &by, u32 &
 // live in registers by age.  The raised digits are read about
 // (1 + (R - 1) / KS_CYC_SEG) times instead of R times, every key value once
 // per 8 or 16 ciphertexts.  Short cycles re-stage the same tiles, which the
-// caches serve.  Same FP64 Barrett products and reductions as mac_kernel
-// (a reduction after every 4 products), so the same residues.
+// caches serve.  Same FP64 Barrett products as mac_kernel, so the same
+// residues.  An accumulator enters a step reduced (|a| <= q/2 + 2) and takes
+// at most 8 products of magnitude <= 7q/8 before the next reduction, so it
+// stays below 7.5 q + 2 < 2^53 (q < 2^50) and every sum is exact: one
+// reduction per key, and one more midway only when a key brings 9 products
+// (8 digits and the folded c0).
 // With c0 given, the block's sum_t phi_t(c0) rides along: its tiles are the
 // same source tiles, so it is staged with the digits and added to the Q
 // limbs of accumulator 0 times P mod q (exact after ModDown, which divides
@@ -313,7 +317,7 @@ mac_cycle_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
                     const double2 kd = kk[d * TT];
                     a0 += mulmod_d(xd, kd.x, q, qinv);
                     a1 += mulmod_d(xd, kd.y, q, qinv);
-                    if ((d & 3) == 3) {
+                    if (XD > 8 && d == 3) {
                         a0 = reduce_d(a0, q, qinv);
                         a1 = reduce_d(a1, q, qinv);
                     }
@@ -448,7 +452,7 @@ mac_short_kernel(DevParams dp, const u64 *x, u64 x_stride, const u64 *raised, co
                 const double2 kd = kk[d * TT];
                 a0 += mulmod_d(xd, kd.x, q, qinv);
                 a1 += mulmod_d(xd, kd.y, q, qinv);
-                if ((d & 3) == 3) {
+                if (XD > 8 && d == 3) {
                     a0 = reduce_d(a0, q, qinv);
                     a1 = reduce_d(a1, q, qinv);
                 }
