@@ -117,6 +117,9 @@ int launch_mul_plain(Ctx *c, const u64 *ct, const u64 *pt, u64 *out, u64 count, 
 // clients go in groups of 8 whose mask values are loaded once into
 // registers and used for every row, so the masks cost 1 / ROWS of a read
 // per output instead of one (the client ciphertexts are read exactly once).
+// The row tiles of one coefficient window are the grid's fastest index, so
+// the workgroups that re-read a window's masks run back to back and find
+// them in L2 rather than HBM.
 // FP64 Barrett products of residues below q come back with |r| < q; a
 // reduction follows every 4 products, so the accumulators stay below
 // 4.5 q < 2^53.  The shape (COEF, ROWS) is a tuning choice ("ms_shape").
@@ -128,9 +131,9 @@ masked_sum_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, con
                   u64 *__restrict__ out)
 {
     const u64 S = (u64)dp.nq << dp.log_n;
-    const u64 r = ((u64)blockIdx.x * MS_TILE + threadIdx.x) * COEF;  // (limb, coefficient), COEF | N
+    const u64 r = ((u64)blockIdx.y * MS_TILE + threadIdx.x) * COEF;  // (limb, coefficient), COEF | N
     if (r >= S) return;
-    const int rows = 2 * len, row0 = blockIdx.y * ROWS;
+    const int rows = 2 * len, row0 = blockIdx.x * ROWS;
     const int l = (int)(r >> dp.log_n);
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     const u64 client_stride = (u64)len * 2 * S;
@@ -205,7 +208,8 @@ template <int COEF, int ROWS>
 static void launch_ms(hipStream_t s, const DevParams &dp, u64 S, const u64 *cts, int n, int len, const u64 *masks,
                       u64 *out)
 {
-    dim3 grid((u32)((S / COEF + MS_TILE - 1) / MS_TILE), (u32)((2 * len + ROWS - 1) / ROWS));
+    // x: row tiles, y: coefficient windows (at most 48 limbs x 2^17 / 256 = 24576)
+    dim3 grid((u32)((2 * len + ROWS - 1) / ROWS), (u32)((S / COEF + MS_TILE - 1) / MS_TILE));
     hipLaunchKernelGGL((masked_sum_kernel<COEF, ROWS>), grid, dim3(MS_TILE), 0, s, dp, cts, n, len, masks, out);
 }
 
@@ -229,9 +233,10 @@ int launch_masked_sum(Ctx *c, const u64 *cts, int n, int len, const u64 *masks, 
 // mask (Enc_pk of its weight), summed over clients before one
 // relinearization per k.  Same structure as the masked sum: a lane owns one
 // coefficient and MA_ROWS packed ciphertexts, clients go in pairs whose mask
-// components sit in registers, every client ciphertext is read once.  FP64
-// Barrett products below q (|r| < q), a reduction after every 4 products per
-// accumulator.
+// components sit in registers, every client ciphertext is read once, and a
+// coefficient window's row tiles run back to back (the grid's fastest index)
+// so that their re-reads of the masks come from L2.  FP64 Barrett products
+// below q (|r| < q), a reduction after every 4 products per accumulator.
 constexpr int MA_TILE = 256;
 constexpr int MA_ROWS = 8;
 
@@ -240,9 +245,9 @@ mask_mul_acc_kernel(DevParams dp, const u64 *__restrict__ cts, int n, int len, i
                     const u64 *__restrict__ masks, u64 *__restrict__ trip)
 {
     const u64 S = (u64)dp.nq << dp.log_n;
-    const u64 r = (u64)blockIdx.x * MA_TILE + threadIdx.x;  // (limb, coefficient)
+    const u64 r = (u64)blockIdx.y * MA_TILE + threadIdx.x;  // (limb, coefficient)
     if (r >= S) return;
-    const int k0 = blockIdx.y * MA_ROWS;
+    const int k0 = blockIdx.x * MA_ROWS;
     const int l = (int)(r >> dp.log_n);
     const double q = dp.mc[l].qd, qinv = dp.mc[l].qinv;
     const u64 client_stride = (u64)row_len * 2 * S;  // a client's row holds row_len ciphertexts, of which len are used
@@ -304,7 +309,8 @@ int launch_mask_mul_acc(Ctx *c, const u64 *cts, int n, int len, int row_len, con
     const u64 S = (u64)c->nq * c->N;
     if (len < 1 || n < 1) return LC_OK;
     if (len > row_len) return fail(c, LC_EINVAL, "chunk longer than the client row");
-    dim3 grid((u32)((S + MA_TILE - 1) / MA_TILE), (u32)((len + MA_ROWS - 1) / MA_ROWS));
+    // x: row tiles, y: coefficient windows (at most 48 limbs x 2^17 / 256 = 24576)
+    dim3 grid((u32)((len + MA_ROWS - 1) / MA_ROWS), (u32)((S + MA_TILE - 1) / MA_TILE));
     hipLaunchKernelGGL(mask_mul_acc_kernel, grid, dim3(MA_TILE), 0, s, c->dp, cts, n, len, row_len, masks, trip);
     LC_HIP(c, hipGetLastError());
     return LC_OK;
