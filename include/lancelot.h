@@ -194,15 +194,17 @@ int lc_rescale(lc_ctx *ctx, const uint64_t *ct_dev, size_t count, int ncomp, int
 /* ---- homomorphic operations (CKKS Scheme Description, evaluation; Methods,
  * Private Distance Evaluation) --------------------------------------------- */
 
-/* out = a -/+ b limb-wise for count ciphertexts of ncomp components. */
+/* out = a -/+ b limb-wise for count ciphertexts of ncomp components.  out
+ * may be a or b itself (in place); any other overlap gives LC_EINVAL. */
 int lc_ct_sub(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out_dev, size_t count,
               int ncomp, void *stream);
 int lc_ct_add(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out_dev, size_t count,
               int ncomp, void *stream);
-/* Triple (a0 b0, a0 b1 + a1 b0, a1 b1) without relinearization. */
+/* Triple (a0 b0, a0 b1 + a1 b0, a1 b1) without relinearization; out3
+ * [count][3][n_q][N] must not overlap a or b (LC_EINVAL). */
 int lc_ct_mul(lc_ctx *ctx, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out3_dev, size_t count,
               void *stream);
-/* Triple (a0^2, 2 a0 a1, a1^2). */
+/* Triple (a0^2, 2 a0 a1, a1^2); out3 must not overlap a (LC_EINVAL). */
 int lc_ct_square(lc_ctx *ctx, const uint64_t *a_dev, uint64_t *out3_dev, size_t count, void *stream);
 /* Relinearization of triples with the s^2 key: out = (d0 + KS0(d2),
  * d1 + KS1(d2)), hybrid key switching (Methods, Lazy Relinearization and
@@ -238,11 +240,13 @@ int lc_rotate_hoisted(lc_ctx *ctx, const uint64_t *ct_dev, size_t count, const i
  * log_n - 1); block b starting at level j0 adds rot_{t 2^j0} for t = 1 ..
  * 2^plan[b] - 1 with one ModUp and one ModDown.  plan NULL = all ones. */
 int lc_rotate_sum(lc_ctx *ctx, uint64_t *ct_dev, size_t count, const int *plan, int nblocks, void *stream);
-/* out = ct * pt per component, pt [n_q][N] NTT domain, one pt per ct. */
+/* out = ct * pt per component, pt [n_q][N] NTT domain, one pt per ct.  out
+ * may be ct itself; any other overlap with ct or pt gives LC_EINVAL. */
 int lc_mul_plain(lc_ctx *ctx, const uint64_t *ct_dev, const uint64_t *pt_dev, uint64_t *out_dev, size_t count,
                  void *stream);
 /* ServerUpdate (Algorithm 1): out[k] = sum_i ct_i[k] * mask_i, client_cts
- * [n][len][2][n_q][N], masks [n][n_q][N] (NTT domain), out [len][2][n_q][N]. */
+ * [n][len][2][n_q][N], masks [n][n_q][N] (NTT domain), out [len][2][n_q][N]
+ * (must not overlap the inputs: LC_EINVAL). */
 int lc_masked_sum(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, const uint64_t *masks_dev,
                   uint64_t *out_dev, void *stream);
 
@@ -250,7 +254,7 @@ int lc_masked_sum(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, c
 
 /* Lazy triples only: for pairs i < j in row-major order, sum over k < len of
  * (ct_i[k] - ct_j[k])^2 as triples.  triples [P][3][n_q][N], P = n(n-1)/2,
- * 2 <= n <= 64. */
+ * 2 <= n <= 64; triples must not overlap the client ciphertexts (LC_EINVAL). */
 int lc_pair_triples(lc_ctx *ctx, const uint64_t *client_cts_dev, int n, int len, uint64_t *triples_dev,
                     void *stream);
 /* Same, adding into triples (which must hold canonical residues): lets a

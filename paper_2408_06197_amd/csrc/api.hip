@@ -106,6 +106,13 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb)
     return x < y + nb && y < x + na;
 }
 
+// Overlap other than the same range: element-wise kernels that read each
+// element before writing the same element may run in place, never shifted.
+static bool partial_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    return overlap(a, na, b, nb) && !(a == b && na == nb);
+}
+
 // Scratch of lc_relin_noalloc: a fixed device array (every GPU the library
 // runs on holds its own copy from module load until the process ends).  In
 // host code `scratch` names a host-side stand-in, never device memory: the
@@ -586,6 +593,9 @@ int lc_ct_sub(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out, si
     CHECK_CTX(x);
     if (ncomp < 1 || ncomp > 3) return fail(c, LC_EINVAL, "ncomp must be 1..3");
     if (count && (!a || !b || !out)) return fail(c, LC_EINVAL, "null buffer");
+    const size_t bytes = count * ncomp * c->nq * c->N * 8;
+    if (partial_overlap(a, bytes, out, bytes) || partial_overlap(b, bytes, out, bytes))
+        return fail(c, LC_EINVAL, "out must equal an input or not overlap it");
     return launch_add_sub(c, a, b, out, count, ncomp, 1, (hipStream_t)stream);
 }
 
@@ -594,6 +604,9 @@ int lc_ct_add(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out, si
     CHECK_CTX(x);
     if (ncomp < 1 || ncomp > 3) return fail(c, LC_EINVAL, "ncomp must be 1..3");
     if (count && (!a || !b || !out)) return fail(c, LC_EINVAL, "null buffer");
+    const size_t bytes = count * ncomp * c->nq * c->N * 8;
+    if (partial_overlap(a, bytes, out, bytes) || partial_overlap(b, bytes, out, bytes))
+        return fail(c, LC_EINVAL, "out must equal an input or not overlap it");
     return launch_add_sub(c, a, b, out, count, ncomp, 0, (hipStream_t)stream);
 }
 
@@ -601,6 +614,9 @@ int lc_ct_mul(lc_ctx *x, const uint64_t *a, const uint64_t *b, uint64_t *out3, s
 {
     CHECK_CTX(x);
     if (count && (!a || !b || !out3)) return fail(c, LC_EINVAL, "null buffer");
+    const size_t S8 = (size_t)c->nq * c->N * 8;
+    if (count && (overlap(a, count * 2 * S8, out3, count * 3 * S8) || overlap(b, count * 2 * S8, out3, count * 3 * S8)))
+        return fail(c, LC_EINVAL, "out3 must not overlap the inputs");
     return launch_tensor(c, a, b, out3, count, (hipStream_t)stream);
 }
 
@@ -608,6 +624,9 @@ int lc_ct_square(lc_ctx *x, const uint64_t *a, uint64_t *out3, size_t count, voi
 {
     CHECK_CTX(x);
     if (count && (!a || !out3)) return fail(c, LC_EINVAL, "null buffer");
+    const size_t S8 = (size_t)c->nq * c->N * 8;
+    if (count && overlap(a, count * 2 * S8, out3, count * 3 * S8))
+        return fail(c, LC_EINVAL, "out3 must not overlap the input");
     return launch_tensor(c, a, nullptr, out3, count, (hipStream_t)stream);
 }
 
@@ -772,6 +791,9 @@ int lc_mul_plain(lc_ctx *x, const uint64_t *ct, const uint64_t *pt, uint64_t *ou
 {
     CHECK_CTX(x);
     if (count && (!ct || !pt || !out)) return fail(c, LC_EINVAL, "null buffer");
+    const size_t S8 = (size_t)c->nq * c->N * 8;
+    if (count && (partial_overlap(ct, count * 2 * S8, out, count * 2 * S8) || overlap(pt, count * S8, out, count * 2 * S8)))
+        return fail(c, LC_EINVAL, "out must equal ct or not overlap it, and must not overlap pt");
     return launch_mul_plain(c, ct, pt, out, count, (hipStream_t)stream);
 }
 
@@ -780,6 +802,10 @@ int lc_masked_sum(lc_ctx *x, const uint64_t *cts, int n, int len, const uint64_t
     CHECK_CTX(x);
     if (n < 1 || n > 4096 || len < 1) return fail(c, LC_EINVAL, "need 1 <= n <= 4096 and len >= 1");
     if (!cts || !masks || !out) return fail(c, LC_EINVAL, "null buffer");
+    const u64 S = (u64)c->nq * c->N;
+    if (overlap(cts, (u64)n * len * 2 * S * 8, out, (u64)len * 2 * S * 8) ||
+        overlap(masks, (u64)n * S * 8, out, (u64)len * 2 * S * 8))
+        return fail(c, LC_EINVAL, "out must not overlap the inputs");
     return launch_masked_sum(c, cts, n, len, masks, out, (hipStream_t)stream);
 }
 
@@ -820,6 +846,8 @@ int lc_pair_triples(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t *tr
     CHECK_CTX(x);
     if (!cts || !triples) return fail(c, LC_EINVAL, "null buffer");
     const u64 S = (u64)c->nq * c->N;
+    if (n >= 2 && len >= 1 && overlap(cts, (u64)n * len * 2 * S * 8, triples, (u64)n * (n - 1) / 2 * 3 * S * 8))
+        return fail(c, LC_EINVAL, "triples must not overlap the client ciphertexts");
     return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, 0, (hipStream_t)stream);
 }
 
@@ -828,6 +856,8 @@ int lc_pair_triples_acc(lc_ctx *x, const uint64_t *cts, int n, int len, uint64_t
     CHECK_CTX(x);
     if (!cts || !triples) return fail(c, LC_EINVAL, "null buffer");
     const u64 S = (u64)c->nq * c->N;
+    if (n >= 2 && len >= 1 && overlap(cts, (u64)n * len * 2 * S * 8, triples, (u64)n * (n - 1) / 2 * 3 * S * 8))
+        return fail(c, LC_EINVAL, "triples must not overlap the client ciphertexts");
     return launch_pair_triples(c, cts, n, len, triples, 3 * S, triples + 2 * S, 3 * S, 1, (hipStream_t)stream);
 }
 

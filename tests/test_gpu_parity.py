@@ -211,6 +211,52 @@ def test_elementwise_bitexact(torch, L, oracle_mod, prm):
     assert np.array_equal(ms, ora.masked_sum(client_cts, masks))
 
 
+def test_elementwise_aliasing(torch, L, oracle_mod):
+    """In-place element-wise calls equal their out-of-place results; outputs that overlap an input any
+    other way (shifted, or of another layout) are rejected before anything runs."""
+    O = oracle_mod
+    ctx, ora, keys = make_pair(L, O, *TINY, seed=9)
+    rng = np.random.default_rng(5)
+    m = rng.integers(-(1 << 20), 1 << 20, size=(8, ctx.N), dtype=np.int64)
+    cts = up(torch, ora.encrypt(1, 0, m, keys["pk"]))  # [8][2][nq][N]
+    a, b = cts[:3].clone(), cts[3:6].clone()
+    want_sub, want_add = ctx.ct_sub(a, b), ctx.ct_add(a, b)
+    x = a.clone()
+    ctx.ct_sub(x, b, out=x)
+    assert torch.equal(x, want_sub)
+    y = b.clone()
+    ctx.ct_add(a, y, out=y)
+    assert torch.equal(y, want_add)
+    pts = up(torch, synth.uniform_residues(6, ctx.q, (3, ctx.N)))
+    want_mp = ctx.mul_plain(a, pts)
+    z = a.clone()
+    ctx.mul_plain(z, pts, out=z)
+    assert torch.equal(z, want_mp)
+    S = 2 * ctx.nq * ctx.N  # words per ciphertext
+    flat = cts.clone().view(-1)
+
+    def view(off, count, ncomp=2):
+        return flat[off: off + count * ncomp * ctx.nq * ctx.N].view(count, ncomp, ctx.nq, ctx.N)
+
+    bad = [
+        lambda: ctx.ct_sub(view(0, 3), view(3 * S, 3), out=view(S // 2, 3)),      # shifted over a
+        lambda: ctx.ct_add(view(0, 3), view(3 * S, 3), out=view(3 * S + 8, 3)),  # shifted over b
+        lambda: ctx.ct_square(view(0, 2), out=view(0, 2, 3)),                   # another layout
+        lambda: ctx.ct_mul(view(0, 2), view(2 * S, 2), out=view(2 * S, 2, 3)),
+        lambda: ctx.mul_plain(view(0, 2), view(2 * S, 1), out=view(2 * S, 2)),  # over pt
+        lambda: ctx.masked_sum(view(0, 4).view(2, 2, 2, ctx.nq, ctx.N), view(4 * S, 1),
+                               out=view(S, 2)),
+        lambda: ctx.pair_triples(view(0, 4).view(2, 2, 2, ctx.nq, ctx.N), out=view(2 * S, 1, 3)),
+    ]
+    before = flat.clone()
+    for i, f in enumerate(bad):
+        with pytest.raises(L.LancelotError) as e:
+            f()
+        assert e.value.code == L.LC_EINVAL, i
+    torch.cuda.synchronize()
+    assert torch.equal(flat, before)  # nothing was launched
+
+
 @pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("log_n,n,ln", [(6, 11, 9), (9, 8, 8), (12, 17, 3)])
 def test_masked_sum_shapes_bitexact(torch, L, oracle_mod, log_n, n, ln, shape):
