@@ -378,7 +378,7 @@ int lc_set_workspace_limit(lc_ctx *ctx, size_t bytes);
  * "fuse_modup" (1 = for 2^10 <= N the ModUp base conversion runs inside the
  * first forward-NTT pass of the raised digits; 0 = a kernel of its own),
  * "ms_shape" (masked-sum lanes: 0 = 1 coefficient x 16 rows, 1 = 2 x 8,
- * 2 = 2 x 16), "ks_streams" (2 = the relinearization / rotate-and-sum
+ * 2 = 2 x 16, the default), "ks_streams" (2 = the relinearization / rotate-and-sum
  * batches of lc_pairwise_sqdist and lc_pairwise_finish alternate between the
  * caller's stream and a second stream of the library's, made on the first
  * such call on that caller stream, forked after the triples and joined

@@ -130,7 +130,7 @@ struct Ctx {
         int mac_cycle_c0 = 1;    // the inner product (walk or gather) also folds sum_t phi_t(c0) into the accumulator
         int mac_cycle_short = 1; // blocks whose tile cycles are at most 2 tiles long skip the walk
         int fuse_modup = 1;   // ModUp conversion fused into the first forward-NTT pass (N >= 2^10)
-        int ms_shape = 0;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
+        int ms_shape = 2;     // masked-sum lane shape: 0 = 1 coefficient x 16 rows, 1 = 2 x 8, 2 = 2 x 16
         int ks_streams = 2;   // streams the batches of a pairwise finish alternate over (1 or 2)
         int hoist_multi = 1;  // literal hoisted rotations stage each source tile once for up to 8 keys
         int mac_xcd = 1;      // cycle-walk / short-cycle workgroups sharing key tiles run on one XCD
