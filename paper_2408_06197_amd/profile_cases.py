@@ -4,6 +4,7 @@
     python -m paper_2408_06197_amd.profile_cases keyswitch  # one rotate-and-sum of 16 ciphertexts
     python -m paper_2408_06197_amd.profile_cases keyswitch fuse_modup=0   # with lc_set_tuning overrides
     python -m paper_2408_06197_amd.profile_cases ntt        # forward + inverse NTT of 64 ciphertexts' limbs
+    python -m paper_2408_06197_amd.profile_cases masked     # one plaintext-mask masked sum (a6)
 
 All run at N = 2^16 with 24 + 4 limbs of 50 bits on random residues, then
 copy 4 GiB with a plain device copy so that each counter can be scaled by
@@ -84,9 +85,31 @@ def ntt(tune, count=64, reps=3):
     _calibration_copy()
 
 
+def masked(tune, n=20, ln=342):
+    """lc_masked_sum over 20 clients x 342 packed ciphertexts (172 GB) with
+    full-range masks, once per masked-sum shape 0, 1, 2 (or the one given)."""
+    ctx = L.Context(LOG_N, (50,) * NQ, (50,) * NP, device=0)
+    for k, v in tune.items():
+        ctx.set_tuning(k, v)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    cts = torch.empty((n, ln, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    masks = torch.empty((n, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    for l in range(NQ):
+        cts[:, :, :, l].random_(0, int(ctx.q[l]), generator=gen)
+        masks[:, l].random_(0, int(ctx.q[l]), generator=gen)
+    out = torch.empty((ln, 2, NQ, 1 << LOG_N), dtype=torch.int64, device="cuda")
+    for shape in ([tune["ms_shape"]] if "ms_shape" in tune else [0, 1, 2]):
+        ctx.set_tuning("ms_shape", shape)
+        ctx.masked_sum(cts, masks, out=out)
+    torch.cuda.synchronize()
+    del cts
+    _calibration_copy()
+
+
 if __name__ == "__main__":
     case = sys.argv[1] if len(sys.argv) > 1 else "pair"
-    cases = {"pair": pair, "keyswitch": keyswitch, "ntt": ntt}
+    cases = {"pair": pair, "keyswitch": keyswitch, "ntt": ntt, "masked": masked}
     if case not in cases:
         sys.exit("cases: " + ", ".join(cases))
     tune = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in sys.argv[2:])
