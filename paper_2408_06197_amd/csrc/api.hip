@@ -726,9 +726,11 @@ int lc_rotate_hoisted(lc_ctx *x, const uint64_t *ct, size_t count, const int *st
     return keyswitch_hoisted(c, ct + S, 2 * S, count, groups.data(), nsteps, (hipStream_t)stream);
 }
 
-int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nblocks, void *stream)
+// The key groups of a rotate-and-sum plan (Methods, Dynamic Hoisting): block
+// b starting at level j0 holds the keys of rot_{t 2^j0}, t = 1 .. 2^plan[b] - 1.
+// With blocks null the plan is only checked.
+static int rotsum_blocks(Ctx *c, const int *plan, int nblocks, std::vector<KsGroup> *blocks)
 {
-    CHECK_CTX(x);
     std::vector<int> pl;
     if (!plan) pl.assign(c->log_n - 1, 1);
     else pl.assign(plan, plan + nblocks);
@@ -738,12 +740,8 @@ int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nb
         total += k;
     }
     if (total != c->log_n - 1) return fail(c, LC_EINVAL, "plan levels must sum to log_n - 1");
-    if (!count) return LC_OK;
-    if (!ct) return fail(c, LC_EINVAL, "null buffer");
-    hipStream_t s = (hipStream_t)stream;
-    const u64 S = (u64)c->nq * c->N;
-    // keys of every block, checked up front
-    std::vector<KsGroup> blocks;
+    if (!blocks) return LC_OK;
+    blocks->clear();
     int j0 = 0;
     for (int k : pl) {
         KsGroup G{};
@@ -759,30 +757,53 @@ int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nb
         // keys t 2^j0 = powers of the step-2^j0 automorphism: the cycle walk applies
         auto cy = c->cycles.find(galois_of_step(c->log_n, 1ll << j0));
         if (G.n > 1 && cy != c->cycles.end() && cy->second.nseg > 0) G.cyc = &cy->second;
-        blocks.push_back(G);
+        blocks->push_back(G);
         j0 += k;
     }
+    return LC_OK;
+}
+
+// Rotate-and-sum of B ciphertexts.  Each block reads one of `io` and `tmp`
+// (B ciphertexts each) and writes the other; the first block reads `tmp`
+// when from_tmp is set, else `io`.  The result is left in `io`, with one copy
+// when the blocks end in `tmp` (from_tmp and an even number of blocks, or an
+// odd number without it).
+static int rotsum_run(Ctx *c, const std::vector<KsGroup> &blocks, u64 *io, u64 *tmp, bool from_tmp, u64 B,
+                      hipStream_t s)
+{
+    const u64 S = (u64)c->nq * c->N;
+    u64 *y = from_tmp ? tmp : io, *z = from_tmp ? io : tmp;
+    for (KsGroup G : blocks) {
+        G.base = y;
+        G.base_stride = 2 * S;
+        G.c0src = y;
+        G.c0_stride = 2 * S;
+        G.out = z;
+        G.out_stride = 2 * S;
+        int rc = keyswitch_hoisted(c, y + S, 2 * S, B, &G, 1, s);
+        if (rc) return rc;
+        std::swap(y, z);
+    }
+    if (y != io) return launch_copy(c, y, io, B * 2 * S, s);
+    return LC_OK;
+}
+
+int lc_rotate_sum(lc_ctx *x, uint64_t *ct, size_t count, const int *plan, int nblocks, void *stream)
+{
+    CHECK_CTX(x);
+    std::vector<KsGroup> blocks;
+    int rc = rotsum_blocks(c, plan, nblocks, nullptr);
+    if (rc || !count) return rc;
+    if (!ct) return fail(c, LC_EINVAL, "null buffer");
+    if ((rc = rotsum_blocks(c, plan, nblocks, &blocks))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const u64 S = (u64)c->nq * c->N;
     u64 chunk = std::min<u64>(count, (u64)c->tune.ks_chunk);
     u64 *other = ws_get(c, WS_ROT, chunk * 2 * S * 8, s);
     if (!other) return LC_ENOMEM;
     for (u64 b0 = 0; b0 < count; b0 += chunk) {
         u64 B = std::min<u64>(chunk, count - b0);
-        u64 *y = ct + b0 * 2 * S, *z = other;
-        for (KsGroup G : blocks) {
-            G.base = y;
-            G.base_stride = 2 * S;
-            G.c0src = y;
-            G.c0_stride = 2 * S;
-            G.out = z;
-            G.out_stride = 2 * S;
-            int rc = keyswitch_hoisted(c, y + S, 2 * S, B, &G, 1, s);
-            if (rc) return rc;
-            std::swap(y, z);
-        }
-        if (y != ct + b0 * 2 * S) {
-            int rc = launch_copy(c, y, ct + b0 * 2 * S, B * 2 * S, s);
-            if (rc) return rc;
-        }
+        if ((rc = rotsum_run(c, blocks, ct + b0 * 2 * S, other, false, B, s))) return rc;
     }
     return LC_OK;
 }
@@ -896,6 +917,12 @@ static int pairwise_finish(lc_ctx *x, Ctx *c, const u64 *d01_base, u64 d01_strid
     const u64 S = (u64)c->nq * c->N;
     const u64 P = (u64)n * (n - 1) / 2;
     const u64 chunk = std::max<u64>(1, std::min<u64>(P, (u64)c->tune.ks_chunk));
+    std::vector<KsGroup> blocks;
+    int rc = rotsum_blocks(c, plan, nblocks, &blocks);
+    if (rc) return rc;
+    // With an odd number of blocks the relinearization writes the rotate
+    // buffer, so that the blocks' ping-pong ends in dist without a copy.
+    const bool from_tmp = blocks.size() % 2 == 1;
     KsGroup g{};
     g.keys[0] = c->rlk;
     g.n = 1;
@@ -907,15 +934,17 @@ static int pairwise_finish(lc_ctx *x, Ctx *c, const u64 *d01_base, u64 d01_strid
         LC_HIP(c, hipEventRecord(ax->fork, s));
         LC_HIP(c, hipStreamWaitEvent(ax->stream, ax->fork, 0));
     }
-    int rc;
     u64 k = 0;
     for (u64 p0 = 0; p0 < P; p0 += chunk, k++) {
         const u64 B = std::min(chunk, P - p0);
         hipStream_t st = (ax && (k & 1)) ? ax->stream : s;
+        u64 *tmp = ws_get(c, WS_ROT, chunk * 2 * S * 8, st);  // the stream's own rotate buffer
+        if (!tmp) return LC_ENOMEM;
+        u64 *io = dist + p0 * 2 * S;
         g.base = d01_base + p0 * d01_stride;
-        g.out = dist + p0 * 2 * S;
+        g.out = from_tmp ? tmp : io;
         if ((rc = keyswitch_hoisted(c, d2 + p0 * d2_stride, d2_stride, B, &g, 1, st))) return rc;
-        if ((rc = lc_rotate_sum(x, dist + p0 * 2 * S, B, plan, nblocks, st))) return rc;
+        if ((rc = rotsum_run(c, blocks, io, tmp, from_tmp, B, st))) return rc;
     }
     if (ax) {
         LC_HIP(c, hipEventRecord(ax->join, ax->stream));
