@@ -578,25 +578,29 @@ def test_ks_tuning_bitexact(torch, L, oracle_mod):
     alternating over two streams or all on one, tiny NTT sub-batches (whole
     digit groups with own-digit limbs skipped), the base conversions fused
     into the transforms or not, and XCD-grouped inner-product workgroups give
-    the oracle's bits."""
+    the oracle's bits, under a plan of nine blocks (the relinearization writes
+    the rotate buffer and the blocks end in the distances) and one of four
+    (the relinearization writes the distances)."""
     O = oracle_mod
     w = KS_W
     ora0 = O.Oracle(w.log_n, w.q_bits, w.p_bits)
-    steps = ora0.rotsum_steps(w.rot_plan)
+    plans = (list(w.rot_plan), [3, 3, 2, 1])
+    steps = sorted(set(st for pl in plans for st in ora0.rotsum_steps(pl)))
     ctx, ora, keys = make_pair(L, O, w.log_n, w.q_bits, w.p_bits, seed=w.crypto_seed, steps=steps)
     upd, m, cts = encrypt_workload(O, ora, keys, w, w.crypto_seed + 1)
-    res = ora.pairwise(cts, keys["rlk"], list(w.rot_plan), [keys["rot"][k] for k in steps])
-    for chunk, sub, mac, fuse, streams, xcd in ((1, 64, 8, 1, 2, 0), (3, 64, 16, 0, 2, 1), (64, 0, 16, 1, 2, 1),
-                                                (64, 0, 8, 0, 2, 0), (3, 64, 8, 1, 2, 0), (3, 0, 16, 1, 1, 1),
-                                                (1, 0, 8, 1, 1, 0)):
-        ctx.set_tuning("ks_chunk", chunk)
-        ctx.set_tuning("ntt_sub_kb", sub)
-        ctx.set_tuning("mac_cts", mac)
-        ctx.set_tuning("fuse_modup", fuse)
-        ctx.set_tuning("ks_streams", streams)
-        ctx.set_tuning("mac_xcd", xcd)
-        dist = ctx.pairwise_sqdist(up(torch, cts), plan=list(w.rot_plan))
-        assert np.array_equal(down(dist), res["dist"]), (chunk, sub, mac, fuse, streams, xcd)
+    for plan in plans:
+        res = ora.pairwise(cts, keys["rlk"], plan, [keys["rot"][k] for k in ora0.rotsum_steps(plan)])
+        for chunk, sub, mac, fuse, streams, xcd in ((1, 64, 8, 1, 2, 0), (3, 64, 16, 0, 2, 1), (64, 0, 16, 1, 2, 1),
+                                                    (64, 0, 8, 0, 2, 0), (3, 64, 8, 1, 2, 0), (3, 0, 16, 1, 1, 1),
+                                                    (1, 0, 8, 1, 1, 0)):
+            ctx.set_tuning("ks_chunk", chunk)
+            ctx.set_tuning("ntt_sub_kb", sub)
+            ctx.set_tuning("mac_cts", mac)
+            ctx.set_tuning("fuse_modup", fuse)
+            ctx.set_tuning("ks_streams", streams)
+            ctx.set_tuning("mac_xcd", xcd)
+            dist = ctx.pairwise_sqdist(up(torch, cts), plan=plan)
+            assert np.array_equal(down(dist), res["dist"]), (plan, chunk, sub, mac, fuse, streams, xcd)
 
 
 def test_set_tuning_rejects_bad_values(L):
